@@ -1,0 +1,165 @@
+/*
+ * dg.h - matrix-free application of interior-penalty DG operators on
+ * hexahedral Q_k meshes by sum factorization, on AMD Instinct MI355X (gfx950).
+ *
+ * The operator is the Jacobian action A z of the DG residual (Section 2.1 of
+ * Kempf, Hess, Muething, Bastian, "Automatic Code Generation for
+ * High-Performance Discontinuous Galerkin Methods on Modern Architectures"):
+ * for the linear problems here, the residual without its u-independent
+ * terms. Two problems are provided:
+ *
+ *   DG_PROBLEM_DIFFREAC  -div(kappa grad u) + c u, symmetric interior penalty
+ *                        (Section 5.2, eq. diffreac_weak), Nitsche terms on
+ *                        the Dirichlet sides;
+ *   DG_PROBLEM_STOKES    velocity Q_k^3 / pressure Q_{k-1} DG Stokes
+ *                        (Section 5.3, eq. stokes_weak), mu = 1.
+ *
+ * Meshes are structured nx*ny*nz hexahedra of the unit cube, cell
+ * e = ex + nx*(ey + ny*ez). Each cell is the image of [0,1]^3 under the
+ * trilinear map of its 8 vertices (Section 2.1).
+ *
+ * Vector layout ("element-blocked, tensor-lexicographic"): a DOF vector holds
+ * one contiguous block per cell, cells in increasing e. Inside a block, the
+ * nodal coefficient at Gauss-Legendre node (i0, i1, i2) sits at
+ * i0 + p*(i1 + p*i2), p = k+1 (x index fastest). A Stokes block is
+ * [u_0 (p^3) | u_1 (p^3) | u_2 (p^3) | pressure (k^3)]. kappa and dkappa use
+ * the same layout over the m^3 volume quadrature points of each cell.
+ *
+ * Conventions for every call:
+ *  - Vectors are caller-owned DEVICE pointers (e.g. torch tensors' data_ptr()),
+ *    contiguous, 16-byte aligned, of the element type selected by
+ *    `precision` (DG_F64: double, DG_F32: float). The library never frees
+ *    them. Outputs are overwritten, never accumulated into. Inputs and
+ *    outputs must not overlap (DG_ERR_ARG).
+ *  - `stream` is a hipStream_t (NULL = the null stream). dg_apply,
+ *    dg_apply_adjoint and dg_load_vector only enqueue work and return;
+ *    dg_solve and dg_mesh_create synchronize the stream before they return.
+ *  - A negative status means the call had no effect; dg_last_error() then
+ *    returns a message (thread-local, valid until the next call on the same
+ *    thread). Argument checks run before any HIP call, so they are usable
+ *    without a GPU. No C++ exception crosses this interface.
+ */
+#ifndef DG_H
+#define DG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dg_mesh dg_mesh; /* opaque; owns its device-side tables */
+
+typedef enum {
+  DG_OK = 0,
+  DG_ERR_ARG = -1,          /* invalid argument, null or overlapping pointers */
+  DG_ERR_UNSUPPORTED = -2,  /* valid but not implemented (degree, rule, geometry) */
+  DG_ERR_DEVICE = -3,       /* a HIP call failed; message from hipGetErrorString */
+  DG_ERR_ALLOC = -4,        /* device or host allocation failed */
+  DG_NOT_CONVERGED = 1,     /* dg_solve hit maxit; x and info are still filled */
+  DG_BREAKDOWN = 2          /* dg_solve met p^T A p <= 0 or a non-finite value */
+} dg_status;
+
+enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1 };
+enum { DG_F64 = 0, DG_F32 = 1 };
+enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
+enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
+enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1 };
+
+/* Mesh and operator description (all fields are read by dg_mesh_create). */
+typedef struct {
+  int32_t nx, ny, nz;       /* cells per direction, >= 1 */
+  int32_t k;                /* polynomial degree (velocity degree for Stokes) */
+  int32_t m;                /* Gauss-Legendre points per direction; 0 -> k + 1 */
+  int32_t problem;          /* DG_PROBLEM_* */
+  double c;                 /* reaction coefficient (diffusion-reaction) */
+  double alpha;             /* penalty parameter (the paper uses 3) */
+  double theta;             /* -1: symmetric interior penalty (the paper's choice) */
+  int32_t penalty_form;     /* 0: gamma_F = alpha k(k+1)|F|/min|T|,
+                               1: gamma_F = alpha k(k+d-1)|F|/min|T| (Section 5.2) */
+  uint32_t dirichlet_mask;  /* bit 2d+s: side s (0 low, 1 high) of direction d is
+                               Dirichlet (Nitsche terms); other sides are natural */
+  const double* vertices;   /* HOST pointer, (nz+1)(ny+1)(nx+1) x 3 coordinates,
+                               x index fastest; NULL = regular grid i/n. Copied. */
+  int32_t kappa_mode;       /* DG_KAPPA_ONE, or DG_KAPPA_QP: kappa per volume
+                               quadrature point is passed to every apply */
+  int32_t kappa_face;       /* DG_KAPPA_FACE_TRACE: kappa on a face is the cell's
+                               interpolant of its point values; DG_KAPPA_FACE_ONE: 1 */
+} dg_mesh_desc;
+
+typedef struct {
+  int64_t nelem;            /* cells */
+  int64_t ndofs;            /* length of a DOF vector */
+  int64_t dofs_per_elem;    /* p^3 (diffusion-reaction) or 3 p^3 + k^3 (Stokes) */
+  int64_t nqp;              /* length of a kappa vector: nelem * m^3 */
+  int32_t p, m;             /* 1D basis nodes and quadrature points */
+  int32_t axis_aligned;     /* 1 when the mesh is the regular grid */
+  double flops_apply;       /* algorithmic flops of one dg_apply (model of the kernels) */
+  double flops_adjoint;     /* ... of one dg_apply_adjoint with dkappa */
+  double bytes_apply[2];    /* compulsory HBM bytes of one dg_apply, [DG_F64, DG_F32] */
+  double bytes_adjoint;     /* ... of one FP64 dg_apply_adjoint with dkappa */
+} dg_mesh_info_t;
+
+typedef struct {
+  double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual) */
+  double inner_rtol;        /* IR: relative residual target of each FP32 inner solve */
+  int32_t maxit;            /* CG: iterations; IR: total inner iterations */
+  int32_t max_outer;        /* IR: refinement steps */
+  int32_t check_every;      /* read the residual norm to the host every n iterations */
+} dg_solve_params;
+
+typedef struct {
+  int32_t iterations;       /* CG iterations (FP64 CG) or total inner iterations (IR) */
+  int32_t outer;            /* IR refinement steps (0 for FP64 CG) */
+  double rel_residual;      /* true ||b - A x||_2 / ||b||_2 in FP64 at exit */
+  double seconds;           /* wall time of the solve, host clock */
+} dg_solve_info;
+
+/* Checks a descriptor without touching the GPU (Section 2.1 restrictions:
+ * cuboid meshes, isotropic degree). DG_OK, DG_ERR_ARG or DG_ERR_UNSUPPORTED. */
+dg_status dg_mesh_desc_validate(const dg_mesh_desc* desc);
+
+/* Builds the 1D Gauss-Legendre rule and nodal Lagrange tables (Section 2.2:
+ * the basis matrices A and D and the face rows), geometry and penalties, and
+ * uploads what the kernels need to the current device. Synchronous. */
+dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out);
+dg_status dg_mesh_destroy(dg_mesh* mesh);
+dg_status dg_mesh_info(const dg_mesh* mesh, dg_mesh_info_t* out);
+
+/* y = A x: one matrix-free operator application by sum factorization
+ * (Algorithm 1 for the cell integrals; facet integrals with the normal
+ * direction contracted first, Section 2.2). kappa: device pointer, nqp values,
+ * required iff kappa_mode == DG_KAPPA_QP, else ignored (may be NULL).
+ * Each output entry is written exactly once; results are bitwise reproducible. */
+dg_status dg_apply(const dg_mesh* mesh, int precision, const void* x, void* y,
+                   const void* kappa, void* stream);
+
+/* ATg = A(kappa)^T g and, if dkappa != NULL, dkappa = dL/dkappa for
+ * L = g^T A(kappa) u (the vector-Jacobian product of dg_apply). Diffusion-
+ * reaction only; u is required iff dkappa != NULL. */
+dg_status dg_apply_adjoint(const dg_mesh* mesh, int precision, const void* g, const void* u,
+                           const void* kappa, void* ATg, void* dkappa, void* stream);
+
+/* Solves A x = b (diffusion-reaction, theta = -1, so A is SPD) by
+ * unpreconditioned CG. DG_SOLVE_CG_F64: FP64 throughout. DG_SOLVE_IR_F32:
+ * iterative refinement, outer residual b - A x in FP64, inner CG on the
+ * FP32 operator with FP64 inner products, FP64 solution update.
+ * b, x: device FP64 vectors; x holds the initial guess on entry. kappa as in
+ * dg_apply (FP64 values; the FP32 operator rounds them). Synchronous. */
+dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
+                   const dg_solve_params* params, dg_solve_info* info, void* stream);
+
+/* Physical coordinates of the volume quadrature points, nqp x 3 doubles into a
+ * HOST buffer (cell-blocked, same order as kappa). */
+dg_status dg_mesh_qpoints(const dg_mesh* mesh, double* xyz);
+
+/* Load vector b_i = sum_q w_q |det J_q| f_q phi_i(x_q) for f given at the volume
+ * quadrature points (device, nqp values); diffusion-reaction, m = k+1. Async. */
+dg_status dg_load_vector(const dg_mesh* mesh, int precision, const void* fq, void* b, void* stream);
+
+const char* dg_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DG_H */

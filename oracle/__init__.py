@@ -32,7 +32,7 @@ convergence and finite differences.
 from .gauss import gauss_legendre
 from .lagrange import lagrange_eval, lagrange_deriv
 from .mesh import HexMesh
-from .problem import Problem
+from .problem import Problem, problem_from_workload
 from .blocks import BlockMatrix
 from .scalar import ScalarDG
 from .stokes import StokesDG
@@ -40,5 +40,5 @@ from .solve import cg
 
 __all__ = [
     "gauss_legendre", "lagrange_eval", "lagrange_deriv", "HexMesh", "Problem",
-    "BlockMatrix", "ScalarDG", "StokesDG", "cg",
+    "BlockMatrix", "ScalarDG", "StokesDG", "cg", "problem_from_workload",
 ]

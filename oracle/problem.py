@@ -125,3 +125,13 @@ def physical_gradients(grad_ref: np.ndarray, J: np.ndarray) -> np.ndarray:
     """grad = J^{-T} grad_ref at every point; grad_ref (P,N,3), J (P,3,3)."""
     Jinv = np.linalg.inv(J)
     return np.einsum("pba,pnb->pna", Jinv, grad_ref)
+
+
+def problem_from_workload(w, n=None, theta=None, kappa=None) -> Problem:
+    """Oracle problem of a workloads.Workload (optionally on an n^3 copy of its mesh)."""
+    import workloads
+    if n is not None:
+        w = w.scaled(n)
+    return Problem(w.n, w.n, w.n, k=w.k, m=w.m, c=w.c, alpha=w.alpha,
+                   theta=w.theta if theta is None else theta, penalty_form=w.penalty_form,
+                   mask=w.mask, vertices=workloads.vertices(w), kappa=kappa)

@@ -1,0 +1,238 @@
+"""Python binding of libdg: matrix-free sum-factorized interior-penalty DG
+operators on MI355X.
+
+Argument marshalling only: every step of the operator runs in the HIP
+kernels of libdg.so. The functions mirror include/dg.h one to one
+(dg_mesh_create, dg_apply, dg_apply_adjoint, dg_solve, ...). Vectors are
+torch tensors on the GPU; the current torch stream is passed to the library.
+There is no CPU fallback: importing fails when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdg.so")
+
+DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_DEVICE, DG_ERR_ALLOC = 0, -1, -2, -3, -4
+DG_NOT_CONVERGED, DG_BREAKDOWN = 1, 2
+DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES = 0, 1
+DG_F64, DG_F32 = 0, 1
+DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
+DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
+DG_SOLVE_CG_F64, DG_SOLVE_IR_F32 = 0, 1
+
+_DTYPE = {DG_F64: torch.float64, DG_F32: torch.float32}
+
+
+class dg_mesh_desc(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("k", ctypes.c_int32), ("m", ctypes.c_int32), ("problem", ctypes.c_int32),
+        ("c", ctypes.c_double), ("alpha", ctypes.c_double), ("theta", ctypes.c_double),
+        ("penalty_form", ctypes.c_int32), ("dirichlet_mask", ctypes.c_uint32),
+        ("vertices", ctypes.POINTER(ctypes.c_double)),
+        ("kappa_mode", ctypes.c_int32), ("kappa_face", ctypes.c_int32),
+    ]
+
+
+class dg_mesh_info_t(ctypes.Structure):
+    _fields_ = [
+        ("nelem", ctypes.c_int64), ("ndofs", ctypes.c_int64), ("dofs_per_elem", ctypes.c_int64),
+        ("nqp", ctypes.c_int64), ("p", ctypes.c_int32), ("m", ctypes.c_int32),
+        ("axis_aligned", ctypes.c_int32), ("flops_apply", ctypes.c_double),
+        ("flops_adjoint", ctypes.c_double), ("bytes_apply", ctypes.c_double * 2),
+        ("bytes_adjoint", ctypes.c_double),
+    ]
+
+
+class dg_solve_params(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", ctypes.c_int32),
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+
+
+class dg_solve_info(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+
+
+# every symbol include/dg.h declares
+EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mesh_info", "dg_apply",
+           "dg_apply_adjoint", "dg_solve", "dg_mesh_qpoints", "dg_load_vector", "dg_last_error")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(python -m paper_1812_08075_amd.build); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, V = ctypes.POINTER, ctypes.c_void_p
+    sig = {
+        "dg_mesh_desc_validate": [P(dg_mesh_desc)],
+        "dg_mesh_create": [P(dg_mesh_desc), V, P(V)],
+        "dg_mesh_destroy": [V],
+        "dg_mesh_info": [V, P(dg_mesh_info_t)],
+        "dg_apply": [V, ctypes.c_int, V, V, V, V],
+        "dg_apply_adjoint": [V, ctypes.c_int, V, V, V, V, V, V],
+        "dg_solve": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
+        "dg_mesh_qpoints": [V, P(ctypes.c_double)],
+        "dg_load_vector": [V, ctypes.c_int, V, V, V],
+        "dg_last_error": [],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = ctypes.c_char_p if name == "dg_last_error" else ctypes.c_int
+    return lib
+
+
+lib = _load()
+
+
+class DGError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"libdg status {status}: {msg}")
+        self.status = status
+
+
+def _check(status: int, allow=()) -> int:
+    if status != DG_OK and status not in allow:
+        raise DGError(status, lib.dg_last_error().decode())
+    return status
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_desc(nx, ny=None, nz=None, k=3, m=0, problem=DG_PROBLEM_DIFFREAC, c=1.0, alpha=3.0, theta=-1.0,
+              penalty_form=0, dirichlet_mask=0x3F, vertices=None, kappa_mode=DG_KAPPA_ONE,
+              kappa_face=DG_KAPPA_FACE_TRACE):
+    """A dg_mesh_desc; `vertices` is an optional float64 numpy array (kept alive on the desc)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    d = dg_mesh_desc(nx, ny, nz, k, m, problem, c, alpha, theta, penalty_form, dirichlet_mask, None,
+                     kappa_mode, kappa_face)
+    if vertices is not None:
+        v = np.ascontiguousarray(vertices, dtype=np.float64)
+        d._vertices_keepalive = v
+        d.vertices = v.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return d
+
+
+def desc_from_workload(w, n=None, theta=None):
+    """Descriptor of a workloads.Workload (optionally on an n^3 copy of its mesh)."""
+    import workloads
+    w = w if n is None else w.scaled(n)
+    verts = workloads.vertices(w)
+    return make_desc(w.n, w.n, w.n, k=w.k, m=w.m, problem=w.problem, c=w.c, alpha=w.alpha,
+                     theta=w.theta if theta is None else theta, penalty_form=w.penalty_form,
+                     dirichlet_mask=w.mask, vertices=verts, kappa_mode=w.kappa_mode)
+
+
+def dg_mesh_desc_validate(desc) -> int:
+    return lib.dg_mesh_desc_validate(ctypes.byref(desc))
+
+
+def dg_mesh_create(desc, stream=None):
+    h = ctypes.c_void_p()
+    _check(lib.dg_mesh_create(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+    return h
+
+
+def dg_mesh_destroy(mesh):
+    _check(lib.dg_mesh_destroy(mesh))
+
+
+def dg_mesh_info(mesh) -> dg_mesh_info_t:
+    out = dg_mesh_info_t()
+    _check(lib.dg_mesh_info(mesh, ctypes.byref(out)))
+    return out
+
+
+def dg_apply(mesh, precision, x, y, kappa=None, stream=None):
+    _check(lib.dg_apply(mesh, precision, _ptr(x), _ptr(y), _ptr(kappa), _stream(stream)))
+
+
+def dg_apply_adjoint(mesh, precision, g, u, kappa, ATg, dkappa=None, stream=None):
+    _check(lib.dg_apply_adjoint(mesh, precision, _ptr(g), _ptr(u), _ptr(kappa), _ptr(ATg), _ptr(dkappa),
+                                _stream(stream)))
+
+
+def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=100000, max_outer=50,
+             check_every=10, stream=None):
+    params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every)
+    info = dg_solve_info()
+    st = _check(lib.dg_solve(mesh, mode, _ptr(b), _ptr(x), _ptr(kappa), ctypes.byref(params),
+                             ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))
+    return st, info
+
+
+def dg_mesh_qpoints(mesh) -> np.ndarray:
+    info = dg_mesh_info(mesh)
+    out = np.empty((info.nqp, 3), dtype=np.float64)
+    _check(lib.dg_mesh_qpoints(mesh, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def dg_load_vector(mesh, precision, fq, b, stream=None):
+    _check(lib.dg_load_vector(mesh, precision, _ptr(fq), _ptr(b), _stream(stream)))
+
+
+class Mesh:
+    """Owning wrapper of a dg_mesh handle with tensor-allocating helpers."""
+
+    def __init__(self, desc, stream=None):
+        self.desc = desc
+        self.handle = dg_mesh_create(desc, stream)
+        self.info = dg_mesh_info(self.handle)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and h.value:
+            lib.dg_mesh_destroy(h)
+            self.handle = None
+
+    @property
+    def ndofs(self) -> int:
+        return int(self.info.ndofs)
+
+    def apply(self, x, kappa=None, out=None):
+        prec = DG_F64 if x.dtype == torch.float64 else DG_F32
+        y = torch.empty_like(x) if out is None else out
+        dg_apply(self.handle, prec, x, y, kappa)
+        return y
+
+    def apply_adjoint(self, g, u=None, kappa=None, want_dkappa=True):
+        prec = DG_F64 if g.dtype == torch.float64 else DG_F32
+        ATg = torch.empty_like(g)
+        dk = torch.empty(int(self.info.nqp), dtype=g.dtype, device=g.device) if want_dkappa else None
+        dg_apply_adjoint(self.handle, prec, g, u, kappa, ATg, dk)
+        return ATg, dk
+
+
+class DGApply(torch.autograd.Function):
+    """y = A(kappa) u; backward returns A^T g and dL/dkappa from dg_apply_adjoint."""
+
+    @staticmethod
+    def forward(ctx, mesh: Mesh, u, kappa):
+        ctx.mesh = mesh
+        ctx.save_for_backward(u, kappa)
+        return mesh.apply(u, kappa)
+
+    @staticmethod
+    def backward(ctx, g):
+        u, kappa = ctx.saved_tensors
+        need_k = ctx.needs_input_grad[2]
+        ATg, dk = ctx.mesh.apply_adjoint(g.contiguous(), u if need_k else None, kappa, want_dkappa=need_k)
+        return None, ATg, dk

@@ -1,0 +1,364 @@
+// C entry points of the DG library: descriptor validation, mesh setup and the
+// operator calls. See include/dg.h for the contract of every function.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <exception>
+#include <new>
+#include <stdexcept>
+#include <string>
+
+#include "internal.h"
+
+namespace {
+thread_local std::string g_last_error;
+
+struct DgError : std::runtime_error {
+  dg_status st;
+  DgError(dg_status s, const std::string& m) : std::runtime_error(m), st(s) {}
+};
+
+[[noreturn]] void fail(dg_status s, const std::string& m) { throw DgError(s, m); }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) fail(DG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class F>
+dg_status guarded(F&& f) {
+  try {
+    return f();
+  } catch (const DgError& e) {
+    g_last_error = e.what();
+    return e.st;
+  } catch (const std::bad_alloc&) {
+    g_last_error = "host allocation failed";
+    return DG_ERR_ALLOC;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DG_ERR_ARG;
+  } catch (...) {
+    g_last_error = "unknown error";
+    return DG_ERR_ARG;
+  }
+}
+
+int quad_points(const dg_mesh_desc& d) { return d.m == 0 ? d.k + 1 : d.m; }
+
+// Checks everything that can be checked without a device.
+void validate(const dg_mesh_desc* d) {
+  if (!d) fail(DG_ERR_ARG, "desc is NULL");
+  if (d->nx < 1 || d->ny < 1 || d->nz < 1) fail(DG_ERR_ARG, "nx, ny, nz must be >= 1");
+  if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES) fail(DG_ERR_ARG, "unknown problem");
+  if (d->k < 1) fail(DG_ERR_ARG, "k must be >= 1");
+  if (d->m < 0) fail(DG_ERR_ARG, "m must be >= 0");
+  if (!std::isfinite(d->c) || !std::isfinite(d->alpha) || !std::isfinite(d->theta))
+    fail(DG_ERR_ARG, "c, alpha and theta must be finite");
+  if (d->alpha < 0) fail(DG_ERR_ARG, "alpha must be >= 0");
+  if (d->penalty_form != 0 && d->penalty_form != 1) fail(DG_ERR_ARG, "penalty_form must be 0 or 1");
+  if (d->dirichlet_mask > 0x3Fu) fail(DG_ERR_ARG, "dirichlet_mask has bits above the six sides");
+  if (d->kappa_mode != DG_KAPPA_ONE && d->kappa_mode != DG_KAPPA_QP) fail(DG_ERR_ARG, "unknown kappa_mode");
+  if (d->kappa_face != DG_KAPPA_FACE_TRACE && d->kappa_face != DG_KAPPA_FACE_ONE)
+    fail(DG_ERR_ARG, "unknown kappa_face");
+  const int64_t nelem = (int64_t)d->nx * d->ny * d->nz;
+  if (nelem > (int64_t)1 << 31) fail(DG_ERR_ARG, "too many cells");
+  if (d->k + 1 > dgi::PMAX) fail(DG_ERR_UNSUPPORTED, "degree k > 7 is not built");
+  if (quad_points(*d) != d->k + 1)
+    fail(DG_ERR_UNSUPPORTED, "only m = k + 1 (collocated Gauss-Legendre basis) is built");
+  if (d->problem == DG_PROBLEM_DIFFREAC) {
+    if (d->vertices) fail(DG_ERR_UNSUPPORTED, "diffusion-reaction runs on the regular (axis-aligned) grid only");
+  } else {
+    if (d->k < 2) fail(DG_ERR_UNSUPPORTED, "Stokes needs k >= 2");
+    if (d->kappa_mode != DG_KAPPA_ONE) fail(DG_ERR_ARG, "Stokes has no kappa");
+  }
+  if (d->vertices) {
+    const int64_t nv = (int64_t)(d->nx + 1) * (d->ny + 1) * (d->nz + 1) * 3;
+    for (int64_t i = 0; i < nv; ++i)
+      if (!std::isfinite(d->vertices[i])) fail(DG_ERR_ARG, "non-finite vertex coordinate");
+  }
+}
+
+double penalty_coef(const dg_mesh_desc& d) {
+  const double k = d.k;
+  return d.penalty_form == 0 ? d.alpha * k * (k + 1) : d.alpha * k * (k + 2);
+}
+
+template <typename T>
+void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
+  const dgi::Tables1D& t = M.tab;
+  const int p = M.p;
+  std::memset(&a, 0, sizeof(a));
+  for (int q = 0; q < p; ++q)
+    for (int j = 0; j < p; ++j) a.D[q * p + j] = (T)t.D[q][j];
+  for (int s = 0; s < 2; ++s)
+    for (int j = 0; j < p; ++j) {
+      a.e[s][j] = (T)t.e[s][j];
+      a.de[s][j] = (T)t.de[s][j];
+    }
+  for (int q = 0; q < p; ++q) a.w[q] = (T)t.wq[q];
+  const int n[3] = {M.desc.nx, M.desc.ny, M.desc.nz};
+  double h[3];
+  for (int d = 0; d < 3; ++d) h[d] = 1.0 / n[d];
+  const double detJ = h[0] * h[1] * h[2];
+  const double coef = penalty_coef(M.desc);
+  for (int d = 0; d < 3; ++d) {
+    a.vs[d] = (T)(detJ / (h[d] * h[d]));
+    a.fs[d] = (T)(detJ / h[d]);
+    a.hinv[d] = (T)(1.0 / h[d]);
+    // |F| / min(|T-|, |T+|) = (|J| / h_d) / |J| on the regular grid, interior and boundary
+    a.gam[d] = (T)(coef / h[d]);
+    a.n[d] = n[d];
+  }
+  a.cmass = (T)(M.desc.c * detJ);
+  a.c_cons = (T)(-1.0);
+  a.c_sym = (T)M.desc.theta;
+  a.nelem = (int32_t)M.nelem;
+  a.mask = M.desc.dirichlet_mask;
+  a.kappa_face_one = M.desc.kappa_face == DG_KAPPA_FACE_ONE;
+}
+
+size_t elem_size(int prec) { return prec == DG_F64 ? sizeof(double) : sizeof(float); }
+
+void check_prec(int prec) {
+  if (prec != DG_F64 && prec != DG_F32) fail(DG_ERR_ARG, "precision must be DG_F64 or DG_F32");
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  if (!a || !b) return false;
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+void check_vec(const void* p, const char* name, size_t align) {
+  if (!p) fail(DG_ERR_ARG, std::string(name) + " is NULL");
+  if ((uintptr_t)p % align) fail(DG_ERR_ARG, std::string(name) + " is not aligned to its element size");
+}
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+}  // namespace
+
+void dg_set_error(const std::string& msg) { g_last_error = msg; }
+
+// The host-side trilinear geometry used by the Stokes setup and dg_mesh_qpoints.
+namespace dgi {
+void cell_corners(const dg_mesh& M, int64_t e, double X[8][3]);
+void stokes_setup(dg_mesh& M);
+}  // namespace dgi
+
+void dgi::cell_corners(const dg_mesh& M, int64_t e, double X[8][3]) {
+  const int nx = M.desc.nx, ny = M.desc.ny;
+  const int64_t ex = e % nx, ey = (e / nx) % ny, ez = e / ((int64_t)nx * ny);
+  for (int c = 0; c < 8; ++c) {
+    const int64_t i = ex + (c & 1), j = ey + ((c >> 1) & 1), l = ez + ((c >> 2) & 1);
+    if (M.vertices.empty()) {
+      X[c][0] = (double)i / M.desc.nx;
+      X[c][1] = (double)j / M.desc.ny;
+      X[c][2] = (double)l / M.desc.nz;
+    } else {
+      const int64_t v = i + (int64_t)(nx + 1) * (j + (int64_t)(ny + 1) * l);
+      for (int a = 0; a < 3; ++a) X[c][a] = M.vertices[3 * v + a];
+    }
+  }
+}
+
+extern "C" {
+
+const char* dg_last_error(void) { return g_last_error.c_str(); }
+
+dg_status dg_mesh_desc_validate(const dg_mesh_desc* desc) {
+  return guarded([&] {
+    validate(desc);
+    return DG_OK;
+  });
+}
+
+dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out) {
+  return guarded([&]() -> dg_status {
+    if (!out) fail(DG_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    validate(desc);
+    dg_mesh* M = new dg_mesh();
+    try {
+      M->desc = *desc;
+      M->desc.vertices = nullptr;
+      M->p = desc->k + 1;
+      M->m = quad_points(*desc);
+      M->kp = desc->k;
+      M->nelem = (int64_t)desc->nx * desc->ny * desc->nz;
+      M->N = desc->problem == DG_PROBLEM_STOKES ? 3 * (int64_t)M->p * M->p * M->p + (int64_t)M->kp * M->kp * M->kp
+                                                : (int64_t)M->p * M->p * M->p;
+      M->ndofs = M->nelem * M->N;
+      M->nqp = M->nelem * (int64_t)M->m * M->m * M->m;
+      M->axis_aligned = desc->vertices == nullptr;
+      if (desc->vertices) {
+        const size_t nv = (size_t)(desc->nx + 1) * (desc->ny + 1) * (desc->nz + 1) * 3;
+        M->vertices.assign(desc->vertices, desc->vertices + nv);
+      }
+      M->tab = dgi::make_tables(M->p, M->m);
+      hip_check(hipGetDevice(&M->device), "hipGetDevice");
+      fill_scalar_args(*M, M->sd);
+      fill_scalar_args(*M, M->sf);
+      if (desc->problem == DG_PROBLEM_STOKES) dgi::stokes_setup(*M);
+      hip_check(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");
+    } catch (...) {
+      dg_mesh_destroy(M);
+      throw;
+    }
+    *out = M;
+    return DG_OK;
+  });
+}
+
+dg_status dg_mesh_destroy(dg_mesh* M) {
+  return guarded([&] {
+    if (!M) return DG_OK;
+    if (M->d_vertices) (void)hipFree(M->d_vertices);
+    if (M->d_gamma) (void)hipFree(M->d_gamma);
+    delete M;
+    return DG_OK;
+  });
+}
+
+dg_status dg_mesh_info(const dg_mesh* M, dg_mesh_info_t* out) {
+  return guarded([&] {
+    if (!M || !out) fail(DG_ERR_ARG, "mesh or out is NULL");
+    std::memset(out, 0, sizeof(*out));
+    out->nelem = M->nelem;
+    out->ndofs = M->ndofs;
+    out->dofs_per_elem = M->N;
+    out->nqp = M->nqp;
+    out->p = M->p;
+    out->m = M->m;
+    out->axis_aligned = M->axis_aligned ? 1 : 0;
+    const double p = M->p, E = (double)M->nelem;
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    if (M->desc.problem == DG_PROBLEM_DIFFREAC) {
+      // per cell, all six faces interior: 3 directions x p^2 lines, each with
+      // two p x p contractions (4p^2), pointwise scaling (p, 2p with kappa) and
+      // two faces (own trace + normal derivative 4p, neighbour 4p, flux 12,
+      // test rows 4p; kappa traces +4p); mass term 2p on the x lines; final
+      // sum of the three directions 2 per DOF
+      const double face = 12 * p + 12 + (kap ? 4 * p : 0);
+      const double line = 4 * p * p + (kap ? 2 * p : p) + 2 * face;
+      out->flops_apply = E * (3 * p * p * line + 2 * p * p * p + 2 * p * p * p);
+      // adjoint: the transposed apply on g, plus the forward contractions of u
+      // (2p^2 per line), volume dkappa products (3p), face dkappa terms
+      // (u, g traces of the neighbour 8p, product 8, test rows 2p)
+      const double adj_line = line + 2 * p * p + 3 * p + 2 * (12 * p + 8);
+      out->flops_adjoint = E * (3 * p * p * adj_line + 4 * p * p * p);
+      out->bytes_apply[0] = (double)M->ndofs * (16 + (kap ? 8 : 0));
+      out->bytes_apply[1] = (double)M->ndofs * (8 + (kap ? 4 : 0));
+      out->bytes_adjoint = (double)M->ndofs * 40;
+    } else {
+      const double kp = M->kp;
+      // per cell: 3 components x 3 gradient contractions forward and back
+      // (18 p^4), pressure interpolation forward and back (2 C_SF(p,kp)),
+      // geometry and pointwise work per point (~220), faces per side with
+      // full gradient traces (~ 3 x 10 p^3 + 30 p^2 per side)
+      const double csf = 2 * (p * kp * kp * kp + p * p * kp * kp + p * p * p * kp);
+      const double face = 3 * (10 * p * p * p) + 60 * p * p;
+      out->flops_apply = E * (18 * p * p * p * p + 2 * csf + 220 * p * p * p + 6 * face);
+      out->bytes_apply[0] = (double)M->ndofs * 16;
+      out->bytes_apply[1] = (double)M->ndofs * 8;
+    }
+    return DG_OK;
+  });
+}
+
+dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, const void* kappa, void* stream) {
+  return guarded([&] {
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    check_prec(precision);
+    const size_t es = elem_size(precision);
+    check_vec(x, "x", es);
+    check_vec(y, "y", es);
+    const size_t nb = (size_t)M->ndofs * es;
+    if (overlap(x, nb, y, nb)) fail(DG_ERR_ARG, "x and y overlap");
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    if (kap) {
+      check_vec(kappa, "kappa", es);
+      if (overlap(kappa, (size_t)M->nqp * es, y, nb)) fail(DG_ERR_ARG, "kappa and y overlap");
+    }
+    if (M->desc.problem == DG_PROBLEM_STOKES) {
+      if (precision != DG_F64) fail(DG_ERR_UNSUPPORTED, "the Stokes operator is built for FP64 only");
+      hip_check(dgi::stokes_apply(*M, (const double*)x, (double*)y, as_stream(stream)), "stokes apply launch");
+      return DG_OK;
+    }
+    hip_check(dgi::scalar_apply(*M, precision, x, y, kap ? kappa : nullptr, false, as_stream(stream)),
+              "apply launch");
+    return DG_OK;
+  });
+}
+
+dg_status dg_apply_adjoint(const dg_mesh* M, int precision, const void* g, const void* u, const void* kappa,
+                           void* ATg, void* dkappa, void* stream) {
+  return guarded([&] {
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "the adjoint is built for diffusion-reaction");
+    check_prec(precision);
+    const size_t es = elem_size(precision);
+    check_vec(g, "g", es);
+    check_vec(ATg, "ATg", es);
+    const size_t nb = (size_t)M->ndofs * es, nk = (size_t)M->nqp * es;
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    if (kap) check_vec(kappa, "kappa", es);
+    if (dkappa) {
+      check_vec(u, "u", es);
+      if (overlap(dkappa, nk, g, nb) || overlap(dkappa, nk, u, nb) || overlap(dkappa, nk, ATg, nb) ||
+          (kap && overlap(dkappa, nk, kappa, nk)))
+        fail(DG_ERR_ARG, "dkappa overlaps another argument");
+      if (overlap(ATg, nb, u, nb)) fail(DG_ERR_ARG, "ATg and u overlap");
+    }
+    if (overlap(ATg, nb, g, nb)) fail(DG_ERR_ARG, "ATg and g overlap");
+    if (kap && overlap(ATg, nb, kappa, nk)) fail(DG_ERR_ARG, "ATg and kappa overlap");
+    hipStream_t s = as_stream(stream);
+    if (!dkappa) {
+      hip_check(dgi::scalar_apply(*M, precision, g, ATg, kap ? kappa : nullptr, true, s), "adjoint launch");
+      return DG_OK;
+    }
+    hip_check(dgi::scalar_adjoint(*M, precision, g, u, kap ? kappa : nullptr, ATg, dkappa, s), "adjoint launch");
+    return DG_OK;
+  });
+}
+
+dg_status dg_mesh_qpoints(const dg_mesh* M, double* xyz) {
+  return guarded([&] {
+    if (!M || !xyz) fail(DG_ERR_ARG, "mesh or xyz is NULL");
+    const int m = M->m;
+    const double* xq = M->tab.xq;
+    for (int64_t e = 0; e < M->nelem; ++e) {
+      double X[8][3];
+      dgi::cell_corners(*M, e, X);
+      for (int q2 = 0; q2 < m; ++q2)
+        for (int q1 = 0; q1 < m; ++q1)
+          for (int q0 = 0; q0 < m; ++q0) {
+            const double t[3] = {xq[q0], xq[q1], xq[q2]};
+            double* o = xyz + 3 * (e * m * m * m + q0 + m * (q1 + m * q2));
+            o[0] = o[1] = o[2] = 0;
+            for (int c = 0; c < 8; ++c) {
+              double wgt = 1;
+              for (int d = 0; d < 3; ++d) wgt *= ((c >> d) & 1) ? t[d] : 1 - t[d];
+              for (int a = 0; a < 3; ++a) o[a] += wgt * X[c][a];
+            }
+          }
+    }
+    return DG_OK;
+  });
+}
+
+dg_status dg_load_vector(const dg_mesh* M, int precision, const void* fq, void* b, void* stream) {
+  return guarded([&] {
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "load vectors are built for diffusion-reaction");
+    check_prec(precision);
+    const size_t es = elem_size(precision);
+    check_vec(fq, "fq", es);
+    check_vec(b, "b", es);
+    if (overlap(fq, (size_t)M->nqp * es, b, (size_t)M->ndofs * es)) fail(DG_ERR_ARG, "fq and b overlap");
+    hip_check(dgi::scalar_load(*M, precision, fq, b, as_stream(stream)), "load vector launch");
+    return DG_OK;
+  });
+}
+
+}  // extern "C"

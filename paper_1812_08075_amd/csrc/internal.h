@@ -1,0 +1,101 @@
+// Internal declarations of the DG library (host side and kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "dg.h"
+
+namespace dgi {
+
+constexpr int PMAX = 8;  // largest number of 1D nodes or points (degree 7)
+
+// 1D Gauss-Legendre rule on [0,1] and nodal Lagrange tables (Section 2.2: the
+// basis matrices A^(i), D^(i) and the face rows used with m_d = 1).
+struct Tables1D {
+  int p = 0;   // basis nodes (k+1)
+  int m = 0;   // quadrature points
+  double xn[PMAX] = {};          // basis nodes = p-point Gauss-Legendre nodes
+  double xq[PMAX] = {};          // quadrature nodes
+  double wq[PMAX] = {};          // quadrature weights
+  double A[PMAX][PMAX] = {};     // A[q][j] = l_j(xq_q)
+  double D[PMAX][PMAX] = {};     // D[q][j] = l_j'(xq_q)
+  double e[2][PMAX] = {};        // e[s][j] = l_j(s), s = 0, 1
+  double de[2][PMAX] = {};       // de[s][j] = l_j'(s)
+};
+
+void gauss_legendre_golub_welsch(int m, double* x, double* w);
+Tables1D make_tables(int p, int m);
+
+// Kernel arguments of the axis-aligned diffusion-reaction kernels (passed by
+// value, so the tables live in the kernel-argument segment and are read with
+// scalar loads: every lane uses the same entry at the same time).
+template <typename T>
+struct ScalarArgs {
+  T D[PMAX * PMAX];    // D[q*P + j] = l_j'(x_q), collocated (m = p)
+  T e[2][PMAX];        // face trace rows
+  T de[2][PMAX];       // face derivative rows (reference coordinates)
+  T w[PMAX];           // quadrature weights
+  T vs[3];             // |J| / h_d^2: volume diffusion scale of direction d
+  T fs[3];             // |J| / h_d: face area element of faces normal to d
+  T hinv[3];           // 1 / h_d
+  T gam[3];            // gamma_F of faces normal to d
+  T cmass;             // c |J|
+  T c_cons, c_sym;     // face term coefficients: (-1, theta) forward, (theta, -1) adjoint
+  int32_t n[3];
+  int32_t nelem;
+  uint32_t mask;       // Dirichlet sides, bit 2d+s
+  int32_t kappa_face_one;
+};
+
+// Kernel arguments of the Stokes kernels (general trilinear geometry).
+struct StokesArgs {
+  double D[PMAX * PMAX];   // velocity D at the velocity nodes (m = p)
+  double Ap[PMAX * PMAX];  // pressure basis at the quadrature points, Ap[q*KP + j]
+  double e[2][PMAX], de[2][PMAX];
+  double ep[2][PMAX];      // pressure trace rows
+  double w[PMAX];
+  double theta;
+  int32_t n[3];
+  int32_t nelem;
+  uint32_t mask;
+};
+
+}  // namespace dgi
+
+struct dg_mesh {
+  dg_mesh_desc desc{};
+  int p = 0, m = 0, kp = 0;    // velocity/scalar nodes, quadrature points, pressure nodes
+  int64_t nelem = 0, N = 0, ndofs = 0, nqp = 0;
+  bool axis_aligned = true;
+  int device = 0;
+  dgi::Tables1D tab;
+  dgi::ScalarArgs<double> sd{};
+  dgi::ScalarArgs<float> sf{};
+  dgi::StokesArgs st{};
+  std::vector<double> vertices;   // host copy (perturbed meshes)
+  double* d_vertices = nullptr;   // device copy
+  double* d_gamma = nullptr;      // per-face penalties [3][faces of direction d]
+  int64_t gamma_off[3] = {0, 0, 0};
+};
+
+namespace dgi {
+// Launchers (defined next to their kernels). They return the launch status.
+hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa,
+                        bool transpose, hipStream_t s);
+hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa,
+                          void* ATg, void* dkappa, hipStream_t s);
+hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s);
+hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
+
+// Vector kernels of the solvers (deterministic fixed-order reductions).
+hipError_t blas_dot_partial(const void* a, const void* b, int prec, int64_t n, double* partial,
+                            int nblk, hipStream_t s);
+int blas_dot_blocks(int64_t n);
+}  // namespace dgi
+
+// Error reporting shared by the C entry points.
+void dg_set_error(const std::string& msg);

@@ -1,0 +1,141 @@
+"""GPU parity of the sum-factorized diffusion-reaction apply against the CPU
+oracle's assembled block-sparse matrix, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import Problem, ScalarDG, problem_from_workload
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12      # relative L2, FP64 (the parity bar)
+TOL32 = 2e-5       # relative L2, FP32 apply: ~ 1e2 x unit roundoff of float
+
+
+def relerr(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def gpu_apply(dg, desc, x, kappa=None, dtype=torch.float64):
+    mesh = dg.Mesh(desc)
+    xt = torch.from_numpy(x).to("cuda", dtype)
+    kt = None if kappa is None else torch.from_numpy(kappa).to("cuda", dtype)
+    y = mesh.apply(xt, kt)
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+def test_q2_4cube_matches_oracle(gpu_lib):
+    dg = gpu_lib
+    w = workloads.WORKLOADS[1]
+    print("case: Q2 4^3 FP64", flush=True)
+    x = workloads.inputs(w, "x")
+    y = gpu_apply(dg, dg.desc_from_workload(w), x)
+    ref = ScalarDG(problem_from_workload(w)).assemble().matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7])
+@pytest.mark.parametrize("shape,theta,mask,c", [((3, 2, 5), -1.0, 0x3F, 1.0), ((2, 3, 1), 1.0, 0x1B, 0.3),
+                                                 ((1, 1, 1), -1.0, 0x00, 2.0)])
+def test_degrees_shapes_masks(gpu_lib, k, shape, theta, mask, c):
+    """Every built degree on ragged meshes (cells not a multiple of the block
+    batch), the non-symmetric variant, Neumann sides and a single cell."""
+    dg = gpu_lib
+    print(f"case: k={k} shape={shape} theta={theta} mask={mask:#x}", flush=True)
+    nx, ny, nz = shape
+    N = (k + 1) ** 3
+    x = workloads.uniform(nx * ny * nz * N, 1000 + k)
+    desc = dg.make_desc(nx, ny, nz, k=k, c=c, theta=theta, dirichlet_mask=mask)
+    y = gpu_apply(dg, desc, x)
+    ref = ScalarDG(Problem(nx, ny, nz, k=k, c=c, theta=theta, mask=mask)).assemble().matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
+@pytest.mark.parametrize("penalty_form", [0, 1])
+def test_penalty_forms(gpu_lib, penalty_form):
+    dg = gpu_lib
+    x = workloads.uniform(3 * 3 * 3 * 64, 77)
+    desc = dg.make_desc(3, k=3, penalty_form=penalty_form, alpha=2.5)
+    y = gpu_apply(dg, desc, x)
+    ref = ScalarDG(Problem(3, 3, 3, k=3, penalty_form=penalty_form, alpha=2.5)).assemble().matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
+@pytest.mark.parametrize("k", [2, 3, 5])
+def test_fp32_apply_error(gpu_lib, k):
+    dg = gpu_lib
+    n = 3
+    x = workloads.uniform(n ** 3 * (k + 1) ** 3, 31)
+    y = gpu_apply(dg, dg.make_desc(n, k=k), x, dtype=torch.float32)
+    ref = ScalarDG(Problem(n, n, n, k=k)).assemble().matvec(x)
+    err = relerr(y, ref)
+    print(f"FP32 apply k={k}: relative L2 error {err:.2e}")
+    assert err < TOL32
+
+
+@pytest.mark.parametrize("face_one", [False, True])
+@pytest.mark.parametrize("theta", [-1.0, 1.0])
+def test_kappa_per_point(gpu_lib, face_one, theta):
+    dg = gpu_lib
+    n, k = 3, 4
+    w = workloads.WORKLOADS[4]
+    kap = workloads.lognormal(n ** 3 * 125, w.seed("kappa"))
+    x = workloads.uniform(n ** 3 * 125, w.seed("x"))
+    desc = dg.make_desc(n, k=k, theta=theta, kappa_mode=dg.DG_KAPPA_QP,
+                        kappa_face=dg.DG_KAPPA_FACE_ONE if face_one else dg.DG_KAPPA_FACE_TRACE)
+    y = gpu_apply(dg, desc, x, kappa=kap)
+    ref = ScalarDG(Problem(n, n, n, k=k, theta=theta, kappa=kap, kappa_face_one=face_one)) \
+        .assemble("explicit").matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
+def test_bitwise_deterministic(gpu_lib):
+    dg = gpu_lib
+    w = workloads.WORKLOADS[2].scaled(12)
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    x = torch.from_numpy(workloads.inputs(w, "x")).cuda()
+    y1 = mesh.apply(x)
+    y2 = mesh.apply(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+
+
+def test_q3_64cube_full_vector(gpu_lib):
+    """The benchmark workload at full size (16.8M DOFs), in the launch
+    configuration the benchmark times, against the oracle's deduplicated BSR."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[2]
+    print("case: Q3 64^3 full size", flush=True)
+    x = workloads.inputs(w, "x")
+    y = gpu_apply(dg, dg.desc_from_workload(w), x)
+    ref = ScalarDG(problem_from_workload(w)).assemble("dedup").matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
+def test_transposed_apply(gpu_lib):
+    """A^T g with the non-symmetric variant (theta = +1), no dkappa."""
+    dg = gpu_lib
+    n, k = 3, 3
+    g = workloads.uniform(n ** 3 * 64, 5)
+    mesh = dg.Mesh(dg.make_desc(n, k=k, theta=1.0))
+    gt = torch.from_numpy(g).cuda()
+    ATg, _ = mesh.apply_adjoint(gt, want_dkappa=False)
+    torch.cuda.synchronize()
+    ref = ScalarDG(Problem(n, n, n, k=k, theta=1.0)).assemble().rmatvec(g)
+    assert relerr(ATg.cpu().numpy(), ref) < TOL64
+
+
+def test_load_vector(gpu_lib):
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5].scaled(3)
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    xyz = dg.dg_mesh_qpoints(mesh.handle)
+    fq = torch.from_numpy(workloads.sin_forcing(xyz, w.c)).cuda()
+    b = torch.empty(mesh.ndofs, dtype=torch.float64, device="cuda")
+    dg.dg_load_vector(mesh.handle, dg.DG_F64, fq, b)
+    torch.cuda.synchronize()
+    op = ScalarDG(problem_from_workload(w))
+    ref = op.load_vector(lambda x: workloads.sin_forcing(x, w.c))
+    assert relerr(b.cpu().numpy(), ref) < 1e-13
