@@ -85,6 +85,22 @@ def bench_apply(dg, w, prec, steps, warmup, cold=False, n=None):
     return mesh, ms
 
 
+def bench_adjoint(dg, w, steps, warmup):
+    import torch
+    import workloads
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    g = torch.from_numpy(workloads.inputs(w, "g")).cuda()
+    u = torch.from_numpy(workloads.inputs(w, "u")).cuda()
+    kap = torch.from_numpy(workloads.inputs(w, "kappa")).cuda()
+    ATg = torch.empty_like(g)
+    dk = torch.empty_like(kap)
+    stream = torch.cuda.current_stream()
+    ms = time_applies(lambda: dg.dg_apply_adjoint(mesh.handle, dg.DG_F64, g, u, kap, ATg, dk, stream),
+                      steps, warmup, stream)
+    info = mesh.info
+    return rates(info, ms, 0, nbytes=info.bytes_adjoint, flops=info.flops_adjoint)
+
+
 def cpu_baseline(target_s=12.0):
     """The oracle's deduplicated block-sparse SpMV of the Q3 operator, timed on
     the host on a 24^3 copy of the benchmark mesh (a bounded sample)."""
@@ -112,6 +128,38 @@ def cpu_baseline(target_s=12.0):
                       f"{reps} applies in {el:.1f} s; host has {os.cpu_count()} logical CPUs"}
 
 
+def bench_solve(dg, rtol=1e-10):
+    """Q5 40^3 manufactured sin problem: plain FP64 CG vs FP32-apply iterative
+    refinement, both to the same true relative residual, from x0 = 0."""
+    import torch
+    import workloads
+    w = workloads.WORKLOADS[5]
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    xyz = dg.dg_mesh_qpoints(mesh.handle)
+    fq = torch.from_numpy(workloads.sin_forcing(xyz, w.c)).cuda()
+    del xyz
+    b = torch.empty(mesh.ndofs, dtype=torch.float64, device="cuda")
+    dg.dg_load_vector(mesh.handle, dg.DG_F64, fq, b)
+    out = {}
+    sol = {}
+    for name, mode in (("cg_f64", dg.DG_SOLVE_CG_F64), ("ir_f32", dg.DG_SOLVE_IR_F32)):
+        log(f"solve {name}")
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=rtol, inner_rtol=1e-5, maxit=200000,
+                               max_outer=20, check_every=20)
+        el = time.perf_counter() - t0
+        out[name] = {"status": st, "seconds": el, "iterations": info.iterations, "outer": info.outer,
+                     "true_rel_residual": info.rel_residual}
+        sol[name] = x
+    out["speedup_ir_over_cg"] = out["cg_f64"]["seconds"] / out["ir_f32"]["seconds"]
+    d = sol["ir_f32"] - sol["cg_f64"]
+    out["rel_diff_ir_vs_cg"] = float(torch.linalg.norm(d) / torch.linalg.norm(sol["cg_f64"]))
+    out["workload"] = w.name
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,6 +168,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solve", action="store_true", help="include the Q5 solve comparison")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="after the timed region, copy the 134 MB input vector 5 times with torch's copy "
+                         "kernel (a known-size reference for HBM traffic counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the multi-GPU sharding of the apply is a design note, "
@@ -135,6 +186,13 @@ def main():
     mesh, ms = bench_apply(dg, w2, dg.DG_F64, args.steps, args.warmup)
     info = mesh.info
     r64 = rates(info, ms, 0)
+    if args.copy_probe:
+        src = torch.from_numpy(workloads.inputs(w2, "x")).cuda()
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     extra = {"apply_q3_f64_warm": r64}
 
     if not args.no_extra:
@@ -150,11 +208,20 @@ def main():
         extra["apply_q5_f64"] = rates(m5.info, ms5, 0)
         _, ms5f = bench_apply(dg, w5, dg.DG_F32, args.steps, args.warmup)
         extra["apply_q5_f32"] = rates(m5.info, ms5f, 1)
+        w3 = workloads.WORKLOADS[3]
+        log("Stokes Q3/Q2 32^3 perturbed FP64")
+        m3, ms3 = bench_apply(dg, w3, dg.DG_F64, args.steps, args.warmup)
+        extra["apply_stokes_f64"] = rates(m3.info, ms3, 0)
+        del m3
         w4 = workloads.WORKLOADS[4]
         log("Q4 FP64 with kappa per point")
         m4, ms4 = bench_apply(dg, w4, dg.DG_F64, args.steps, args.warmup)
         extra["apply_q4_kappa_f64"] = rates(m4.info, ms4, 0)
+        log("Q4 FP64 adjoint (A^T g and dL/dkappa)")
+        extra["adjoint_q4_kappa_f64"] = bench_adjoint(dg, w4, args.steps, args.warmup)
         del m4, m5
+    if args.solve:
+        extra["solve_q5_40cube"] = bench_solve(dg)
 
     out = {
         "metric": "DOFs/s per DG operator apply (FP64 vs FP32+refine) + % roofline, Q3-Q5",

@@ -49,6 +49,10 @@ struct ScalarArgs {
   int32_t nelem;
   uint32_t mask;       // Dirichlet sides, bit 2d+s
   int32_t kappa_face_one;
+  // block order: a block is a chunk of up to EB consecutive cells of one x-row;
+  // blocks are swept as (slab of sz z-planes, y, z within the slab, chunk)
+  int32_t nchunk;      // chunks per x-row
+  int32_t sz;          // z-planes per slab
 };
 
 // Kernel arguments of the Stokes kernels (general trilinear geometry).
@@ -58,6 +62,7 @@ struct StokesArgs {
   double e[2][PMAX], de[2][PMAX];
   double ep[2][PMAX];      // pressure trace rows
   double w[PMAX];
+  double xq[PMAX];         // quadrature points (= velocity nodes)
   double theta;
   int32_t n[3];
   int32_t nelem;

@@ -22,16 +22,20 @@
 //    first) sit at the two ends of every d-line: the own trace u and its
 //    normal derivative are dot products of the line with the rows
 //    l_j(s), l_j'(s); the neighbour's trace comes from the neighbour's
-//    matching line, read from global memory (L2). The flux is formed per face
-//    point and multiplied back with the same rows onto the own line only.
-//    Each face is thus evaluated by both its cells (element-centric), every
-//    output value has exactly one writer, there are no atomics, and results
-//    are bitwise reproducible.
-//  * The x and y line results go through LDS, the z line stays in registers;
-//    the sum is written once, so HBM sees one read of x (plus kappa) and one
-//    write of y per apply. Neighbour lines are re-reads served by L2: the
-//    block order is made XCD-aware so that each XCD walks a contiguous slab
-//    of cells.
+//    matching line. The flux is formed per face point and multiplied back
+//    with the same rows onto the own line only. Each face is thus evaluated
+//    by both its cells (element-centric): every output value has exactly one
+//    writer, there are no atomics, and results are bitwise reproducible.
+//  * A block is a chunk of up to EB consecutive cells of one x-row, so its
+//    cells are contiguous in memory (one coalesced load into LDS) and
+//    x-neighbours inside the chunk are read from LDS. Blocks are swept in
+//    the order (slab of z-planes, y, z within the slab, chunk) and the block
+//    order is made XCD-aware (each XCD walks one contiguous range of the
+//    sweep), so the y- and z-neighbour lines a block reads were loaded
+//    shortly before by another block of the same XCD and are served by its
+//    L2: HBM sees about one read of x (plus kappa) and one write of y.
+//  * The x and y line results go through LDS (padded strides against bank
+//    conflicts), the z line stays in registers; the sum is written once.
 //  * The same kernel applies A^T: swapping the coefficients of the two
 //    non-symmetric face terms (consistency term and theta term) transposes
 //    the face bilinear form; the cell terms are symmetric.
@@ -40,12 +44,58 @@
 namespace dgi {
 namespace {
 
+// LDS layout of one cell block: node (i0, i1, i2) at i0 + S1 i1 + S2 i2,
+// cells NP apart. Padded strides break the power-of-two bank patterns of the
+// three line directions.
+template <int P>
+struct Layout {
+  static constexpr int S1 = P, S2 = P * P, NP = P * P * P;
+};
+template <>
+struct Layout<4> {
+  static constexpr int S1 = 4, S2 = 19, NP = 76;
+};
+template <>
+struct Layout<6> {
+  static constexpr int S1 = 6, S2 = 39, NP = 244;
+};
+template <>
+struct Layout<7> {
+  static constexpr int S1 = 7, S2 = 52, NP = 369;
+};
+template <>
+struct Layout<8> {
+  static constexpr int S1 = 9, S2 = 72, NP = 576;
+};
+
 // Bijective block renumbering: hardware block b runs on XCD b % 8; give each
 // XCD a contiguous range of logical blocks so its L2 holds the neighbours.
-__device__ inline int xcd_swizzle(int b, int G) {
+__device__ __forceinline__ int xcd_swizzle(int b, int G) {
   const int q = G >> 3, r = G & 7;
   const int xcd = b & 7, idx = b >> 3;
   return xcd * q + min(xcd, r) + idx;
+}
+
+struct BlockCoord {
+  int chunk, ey, ez;
+};
+
+// Logical block t -> (chunk, y, z) in the sweep order (slab, y, z in slab, chunk).
+template <typename T>
+__device__ __forceinline__ BlockCoord block_coord(int t, const ScalarArgs<T>& a) {
+  const int nc = a.nchunk, ny = a.n[1], nz = a.n[2], sz = a.sz;
+  const int per_slab = nc * ny * sz;
+  const int slab = t / per_slab;
+  const int rem = t - slab * per_slab;
+  const int hz = min(sz, nz - slab * sz);
+  const int ey = rem / (nc * hz);
+  const int rem2 = rem - ey * nc * hz;
+  const int ezi = rem2 / nc;
+  BlockCoord c;
+  c.chunk = rem2 - ezi * nc;
+  c.ey = ey;
+  c.ez = slab * sz + ezi;
+  return c;
 }
 
 template <int P>
@@ -54,29 +104,32 @@ struct CellsPerBlock {
   static constexpr int value = (256 / (P * P)) > 0 ? (256 / (P * P)) : 1;
 };
 
-// Stride between consecutive nodes of a line in direction DIR inside a cell.
-template <int P, int DIR>
-struct LineStride {
-  static constexpr int value = DIR == 0 ? 1 : (DIR == 1 ? P : P * P);
+template <int P>
+struct AdjCellsPerBlock {
+  static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
 };
 
-// One 1D line of one cell in direction DIR: volume terms of that direction,
-// plus both faces normal to DIR at the line's two ends. `off` is the offset
-// of the line's first node in the cell block; (ta, tb) are its two tangential
-// node indices (for the tensor quadrature weights).
-template <int P, typename T, bool KAPPA, int DIR>
-__device__ __forceinline__ void line_apply(const T* __restrict__ sxe, const T* __restrict__ ske, int off, int ta,
-                                           int tb, int64_t e, int ecd, int64_t estride,
-                                           const T* __restrict__ x, const T* __restrict__ kappa,
-                                           const ScalarArgs<T>& a, bool mass, T* out) {
+// Copies nvalid contiguous cell blocks from global memory into the padded LDS layout.
+template <int P, typename T>
+__device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase, int nvalid,
+                                           int nthreads) {
   constexpr int N = P * P * P;
-  constexpr int S = LineStride<P, DIR>::value;
-  T v[P], kv[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    v[j] = sxe[off + j * S];
-    kv[j] = KAPPA ? ske[off + j * S] : T(1);
+  using Ly = Layout<P>;
+  for (int i = threadIdx.x; i < nvalid * N; i += nthreads) {
+    const int le = i / N, l = i - le * N;
+    const int i2 = l / (P * P), i1 = (l / P) % P, i0 = l % P;
+    s[le * Ly::NP + i0 + Ly::S1 * i1 + Ly::S2 * i2] = g[gbase + i];
   }
+}
+
+// Volume and face work of one 1D line of one cell in direction DIR.
+//  v, kv: the line's values and kappa at its nodes; nb[s], nk[s]: the
+//  neighbour's matching line across side s (unused when !has_nb[s]);
+//  (ta, tb): tangential node indices (tensor weights); mass: add c w |J| u.
+template <int P, typename T, bool KAPPA, int DIR>
+__device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
+                                           const bool* has_nb, int ta, int tb, const ScalarArgs<T>& a, bool mass,
+                                           T* out) {
   const T wt = a.w[ta] * a.w[tb];
   // cell: r_q = kappa_q w_q |J|/h^2 (D v)_q, out = D^T r
   T r[P];
@@ -104,12 +157,11 @@ __device__ __forceinline__ void line_apply(const T* __restrict__ sxe, const T* _
   // faces at both ends of the line
   const T fw = wt * a.fs[DIR];
   const T hi = a.hinv[DIR];
-  const int nd = a.n[DIR];
+  const bool face_kappa = KAPPA && !a.kappa_face_one;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const bool has_nb = s ? (ecd < nd - 1) : (ecd > 0);
     const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
-    if (!has_nb && !dirichlet) continue;
+    if (!has_nb[s] && !dirichlet) continue;
     T uT = T(0), dT = T(0);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -117,32 +169,28 @@ __device__ __forceinline__ void line_apply(const T* __restrict__ sxe, const T* _
       dT = fma(a.de[s][j], v[j], dT);
     }
     T kT = T(1);
-    if (KAPPA && !a.kappa_face_one) {
+    if (face_kappa) {
       kT = T(0);
 #pragma unroll
       for (int j = 0; j < P; ++j) kT = fma(a.e[s][j], kv[j], kT);
     }
-    const T sg = s ? T(1) : T(-1);          // outward normal = sg * e_DIR
-    const T dnuT = sg * hi * dT;            // outward normal derivative of the own trace
+    const T sg = s ? T(1) : T(-1);  // outward normal = sg * e_DIR
+    const T dnuT = sg * hi * dT;    // outward normal derivative of the own trace
     T Rv, Rdv;
-    if (has_nb) {
-      const int64_t nb = s ? e + estride : e - estride;
-      const T* __restrict__ xn = x + nb * N + off;
+    if (has_nb[s]) {
       T uN = T(0), dN = T(0);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const T wv = xn[j * S];
-        uN = fma(a.e[1 - s][j], wv, uN);
-        dN = fma(a.de[1 - s][j], wv, dN);
+        uN = fma(a.e[1 - s][j], nb[s][j], uN);
+        dN = fma(a.de[1 - s][j], nb[s][j], dN);
       }
       T kN = T(1);
-      if (KAPPA && !a.kappa_face_one) {
-        const T* __restrict__ kn = kappa + nb * N + off;
+      if (face_kappa) {
         kN = T(0);
 #pragma unroll
-        for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], kn[j * S], kN);
+        for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], nk[s][j], kN);
       }
-      const T dnuN = -sg * hi * dN;         // the neighbour's outward normal is opposite
+      const T dnuN = -sg * hi * dN;  // the neighbour's outward normal is opposite
       const T jump = uT - uN;
       Rv = T(0.5) * a.c_cons * (kT * dnuT - kN * dnuN) + a.gam[DIR] * jump;
       Rdv = T(0.5) * a.c_sym * kT * jump;
@@ -157,25 +205,73 @@ __device__ __forceinline__ void line_apply(const T* __restrict__ sxe, const T* _
   }
 }
 
+// Reads the line of direction DIR at (ta, tb) of LDS cell block `sc`.
+template <int P, typename T, int DIR>
+__device__ __forceinline__ void lds_line(const T* __restrict__ sc, int ta, int tb, T* v) {
+  using Ly = Layout<P>;
+  const int off = DIR == 0 ? Ly::S1 * ta + Ly::S2 * tb : (DIR == 1 ? ta + Ly::S2 * tb : ta + Ly::S1 * tb);
+  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? Ly::S1 : Ly::S2);
+#pragma unroll
+  for (int j = 0; j < P; ++j) v[j] = sc[off + j * S];
+}
+
+// Reads the line of direction DIR at (ta, tb) of the global cell block at `base`.
+template <int P, typename T, int DIR>
+__device__ __forceinline__ void global_line(const T* __restrict__ g, uint32_t base, int ta, int tb, T* v) {
+  constexpr int L = P * P;
+  const uint32_t off = base + (DIR == 0 ? P * ta + L * tb : (DIR == 1 ? ta + L * tb : ta + P * tb));
+  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? P : L);
+#pragma unroll
+  for (int j = 0; j < P; ++j) v[j] = g[off + j * S];
+}
+
+// Neighbour lines of direction DIR for both sides (x-neighbours inside the
+// chunk come from LDS, everything else from global memory / L2).
+template <int P, typename T, int DIR>
+__device__ __forceinline__ void neighbor_lines(const T* __restrict__ s, const T* __restrict__ g, uint32_t e,
+                                               int le, int nvalid, int ecd, int nd, uint32_t estride, int ta,
+                                               int tb, T (*nb)[P], bool* has) {
+  constexpr int N = P * P * P;
+  using Ly = Layout<P>;
+  has[0] = ecd > 0;
+  has[1] = ecd < nd - 1;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    if (!has[side]) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) nb[side][j] = T(0);
+      continue;
+    }
+    const int lnb = side ? le + 1 : le - 1;
+    if (DIR == 0 && lnb >= 0 && lnb < nvalid) {
+      lds_line<P, T, 0>(s + lnb * Ly::NP, ta, tb, nb[side]);
+    } else {
+      const uint32_t en = side ? e + estride : e - estride;
+      global_line<P, T, DIR>(g, en * N, ta, tb, nb[side]);
+    }
+  }
+}
+
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
                    const ScalarArgs<T> a) {
   constexpr int EB = CellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
-  __shared__ T sx[EB * N];
-  __shared__ T sk[KAPPA ? EB * N : 1];
-  __shared__ T sy0[EB * N];
-  __shared__ T sy1[EB * N];
+  using Ly = Layout<P>;
+  __shared__ T sx[EB * Ly::NP];
+  __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
+  __shared__ T sy0[EB * Ly::NP];
+  __shared__ T sy1[EB * Ly::NP];
 
-  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int64_t ebase = (int64_t)blk * EB;
-  const int nvalid = (int)min((int64_t)EB, (int64_t)a.nelem - ebase);
-  const T* __restrict__ xb = x + ebase * N;
-  for (int i = threadIdx.x; i < nvalid * N; i += NT) {
-    sx[i] = xb[i];
-    if (KAPPA) sk[i] = kappa[ebase * N + i];
-  }
+  const BlockCoord bc = block_coord(xcd_swizzle(blockIdx.x, gridDim.x), a);
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int ex0 = bc.chunk * EB;
+  const int nvalid = min(EB, nx - ex0);
+  const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
+  const uint32_t gbase = (row + ex0) * N;
+  load_cells<P, T>(sx, x, gbase, nvalid, NT);
+  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
   __syncthreads();
 
   const int le = threadIdx.x / L;
@@ -184,92 +280,46 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const int ta = li % P, tb = li / P;
   T out2[P];
   if (active) {
-    const int64_t e = ebase + le;
-    const int n0 = a.n[0], n1 = a.n[1];
-    const int ex = (int)(e % n0), ey = (int)((e / n0) % n1), ez = (int)(e / ((int64_t)n0 * n1));
-    const T* sxe = sx + le * N;
-    const T* ske = KAPPA ? sk + le * N : nullptr;
-    T out[P];
+    const int ex = ex0 + le;
+    const uint32_t e = row + ex;
+    const T* sxe = sx + le * Ly::NP;
+    const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
+    T v[P], kv[P], out[P];
+    T nb[2][P], nk[2][P];
+    bool has[2];
     // lines along x: (i1, i2) = (ta, tb)
-    line_apply<P, T, KAPPA, 0>(sxe, ske, ta * P + tb * L, ta, tb, e, ex, 1, x, kappa, a, true, out);
+    lds_line<P, T, 0>(sxe, ta, tb, v);
+    if (KAPPA) lds_line<P, T, 0>(ske, ta, tb, kv);
+    neighbor_lines<P, T, 0>(sx, x, e, le, nvalid, ex, nx, 1u, ta, tb, nb, has);
+    if (KAPPA) neighbor_lines<P, T, 0>(sk, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, nk, has);
+    line_apply<P, T, KAPPA, 0>(v, kv, nb, nk, has, ta, tb, a, true, out);
 #pragma unroll
-    for (int i = 0; i < P; ++i) sy0[le * N + ta * P + tb * L + i] = out[i];
+    for (int i = 0; i < P; ++i) sy0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = out[i];
     // lines along y: (i0, i2) = (ta, tb)
-    line_apply<P, T, KAPPA, 1>(sxe, ske, ta + tb * L, ta, tb, e, ey, n0, x, kappa, a, false, out);
+    lds_line<P, T, 1>(sxe, ta, tb, v);
+    if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
+    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb, has);
+    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk, has);
+    line_apply<P, T, KAPPA, 1>(v, kv, nb, nk, has, ta, tb, a, false, out);
 #pragma unroll
-    for (int i = 0; i < P; ++i) sy1[le * N + ta + tb * L + i * P] = out[i];
+    for (int i = 0; i < P; ++i) sy1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = out[i];
     // lines along z: (i0, i1) = (ta, tb), kept in registers
-    line_apply<P, T, KAPPA, 2>(sxe, ske, ta + tb * P, ta, tb, e, ez, (int64_t)n0 * n1, x, kappa, a, false,
-                               out2);
+    lds_line<P, T, 2>(sxe, ta, tb, v);
+    if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
+    const uint32_t nxy = (uint32_t)nx * ny;
+    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb, has);
+    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk, has);
+    line_apply<P, T, KAPPA, 2>(v, kv, nb, nk, has, ta, tb, a, false, out2);
   }
   __syncthreads();
   if (active) {
-    const int64_t e = ebase + le;
-    const int off = ta + tb * P;
-    T* __restrict__ ye = y + e * N;
+    const uint32_t e = row + ex0 + le;
+    const int lo = le * Ly::NP + ta + Ly::S1 * tb;
+    T* __restrict__ ye = y + e * N + ta + P * tb;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int idx = off + j * L;
-      ye[idx] = sy0[le * N + idx] + sy1[le * N + idx] + out2[j];
-    }
+    for (int j = 0; j < P; ++j) ye[j * L] = sy0[lo + j * Ly::S2] + sy1[lo + j * Ly::S2] + out2[j];
   }
 }
-
-// b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
-template <int P, typename T>
-__global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const ScalarArgs<T> a, int64_t n) {
-  constexpr int N = P * P * P;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  const int l = (int)(i % N);
-  const int i0 = l % P, i1 = (l / P) % P, i2 = l / (P * P);
-  const T detJ = a.vs[0] / (a.hinv[0] * a.hinv[0]);  // |J| = vs_0 h_0^2
-  b[i] = (a.w[i0] * a.w[i1] * a.w[i2] * detJ) * f[i];
-}
-
-template <int P, typename T>
-hipError_t launch_apply(const dg_mesh& M, const ScalarArgs<T>& a, const T* x, T* y, const T* kappa,
-                        hipStream_t s) {
-  constexpr int EB = CellsPerBlock<P>::value;
-  const int64_t G = (M.nelem + EB - 1) / EB;
-  if (G > 0x7fffffff) return hipErrorInvalidValue;
-  if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
-  else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
-  return hipGetLastError();
-}
-
-template <typename T>
-hipError_t dispatch_apply(const dg_mesh& M, const ScalarArgs<T>& a, const T* x, T* y, const T* kappa,
-                          hipStream_t s) {
-  switch (M.p) {
-    case 2: return launch_apply<2, T>(M, a, x, y, kappa, s);
-    case 3: return launch_apply<3, T>(M, a, x, y, kappa, s);
-    case 4: return launch_apply<4, T>(M, a, x, y, kappa, s);
-    case 5: return launch_apply<5, T>(M, a, x, y, kappa, s);
-    case 6: return launch_apply<6, T>(M, a, x, y, kappa, s);
-    case 7: return launch_apply<7, T>(M, a, x, y, kappa, s);
-    case 8: return launch_apply<8, T>(M, a, x, y, kappa, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <typename T>
-hipError_t dispatch_load(const dg_mesh& M, const ScalarArgs<T>& a, const T* f, T* b, hipStream_t s) {
-  const int64_t n = M.ndofs;
-  const unsigned G = (unsigned)((n + 255) / 256);
-  switch (M.p) {
-#define DG_LOAD_CASE(PP) \
-  case PP: hipLaunchKernelGGL((k_scalar_load<PP, T>), dim3(G), dim3(256), 0, s, f, b, a, n); break;
-    DG_LOAD_CASE(2) DG_LOAD_CASE(3) DG_LOAD_CASE(4) DG_LOAD_CASE(5) DG_LOAD_CASE(6) DG_LOAD_CASE(7)
-    DG_LOAD_CASE(8)
-#undef DG_LOAD_CASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
-}
-
 
 // ---------------------------------------------------------------------------
 // Adjoint: A^T g and dL/dkappa for L = g^T A(kappa) u.
@@ -284,23 +334,11 @@ hipError_t dispatch_load(const dg_mesh& M, const ScalarArgs<T>& a, const T* f, T
 //   dI/dkappa_T = 1/2 (c_cons d_nu u_T (g_T - g_N) + c_sym (u_T - u_N) d_nu g_T)
 // (c_cons = -1, c_sym = theta; on Dirichlet sides without the 1/2 and N).
 template <int P, typename T, bool KAPPA, int DIR>
-__device__ __forceinline__ void line_adjoint(const T* __restrict__ sge, const T* __restrict__ sue,
-                                             const T* __restrict__ ske, int off, int ta, int tb, int64_t e,
-                                             int ecd, int64_t estride, const T* __restrict__ g,
-                                             const T* __restrict__ u, const T* __restrict__ kappa,
-                                             const ScalarArgs<T>& a, bool mass, T* outg, T* outk) {
-  constexpr int N = P * P * P;
-  constexpr int S = LineStride<P, DIR>::value;
-  // forward face coefficients; the transposed apply uses them swapped
-  const T cf_cons = a.c_cons, cf_sym = a.c_sym;
-  const T ca_cons = a.c_sym, ca_sym = a.c_cons;
-  T v[P], uu[P], kv[P];
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    v[j] = sge[off + j * S];
-    uu[j] = sue[off + j * S];
-    kv[j] = KAPPA ? ske[off + j * S] : T(1);
-  }
+__device__ __forceinline__ void line_adjoint(const T* v, const T* uu, const T* kv, const T (*gn)[P],
+                                             const T (*un)[P], const T (*kn)[P], const bool* has_nb, int ta,
+                                             int tb, const ScalarArgs<T>& a, bool mass, T* outg, T* outk) {
+  const T cf_cons = a.c_cons, cf_sym = a.c_sym;  // forward coefficients
+  const T ca_cons = a.c_sym, ca_sym = a.c_cons;  // transposed apply
   const T wt = a.w[ta] * a.w[tb];
   const T vsw = a.vs[DIR] * wt;
   T r[P];
@@ -330,13 +368,14 @@ __device__ __forceinline__ void line_adjoint(const T* __restrict__ sge, const T*
   }
   const T fw = wt * a.fs[DIR];
   const T hi = a.hinv[DIR];
-  const int nd = a.n[DIR];
+  // kappa values on faces (traces) exist only with kappa per point; the face part of
+  // dkappa exists whenever faces use the trace reading (kappa = 1 mode included)
   const bool face_kappa = KAPPA && !a.kappa_face_one;
+  const bool face_dk = !a.kappa_face_one;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
-    const bool has_nb = s ? (ecd < nd - 1) : (ecd > 0);
     const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
-    if (!has_nb && !dirichlet) continue;
+    if (!has_nb[s] && !dirichlet) continue;
     T gT = T(0), dgT = T(0), uT = T(0), duT = T(0);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
@@ -354,24 +393,19 @@ __device__ __forceinline__ void line_adjoint(const T* __restrict__ sge, const T*
     const T sg = s ? T(1) : T(-1);
     const T dnug = sg * hi * dgT, dnuu = sg * hi * duT;
     T Rv, Rdv, dI;
-    if (has_nb) {
-      const int64_t nb = s ? e + estride : e - estride;
-      const T* __restrict__ gn = g + nb * N + off;
-      const T* __restrict__ un = u + nb * N + off;
+    if (has_nb[s]) {
       T gN = T(0), dgN = T(0), uN = T(0);
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const T gv = gn[j * S];
-        gN = fma(a.e[1 - s][j], gv, gN);
-        dgN = fma(a.de[1 - s][j], gv, dgN);
-        uN = fma(a.e[1 - s][j], un[j * S], uN);
+        gN = fma(a.e[1 - s][j], gn[s][j], gN);
+        dgN = fma(a.de[1 - s][j], gn[s][j], dgN);
+        uN = fma(a.e[1 - s][j], un[s][j], uN);
       }
       T kN = T(1);
       if (face_kappa) {
-        const T* __restrict__ kn = kappa + nb * N + off;
         kN = T(0);
 #pragma unroll
-        for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], kn[j * S], kN);
+        for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], kn[s][j], kN);
       }
       const T dnugN = -sg * hi * dgN;
       const T jg = gT - gN;
@@ -387,7 +421,7 @@ __device__ __forceinline__ void line_adjoint(const T* __restrict__ sge, const T*
     Rdv *= fw * sg * hi;
 #pragma unroll
     for (int i = 0; i < P; ++i) outg[i] = fma(Rv, a.e[s][i], fma(Rdv, a.de[s][i], outg[i]));
-    if (face_kappa) {
+    if (face_dk) {
       dI *= fw;
 #pragma unroll
       for (int j = 0; j < P; ++j) outk[j] = fma(dI, a.e[s][j], outk[j]);
@@ -395,10 +429,23 @@ __device__ __forceinline__ void line_adjoint(const T* __restrict__ sge, const T*
   }
 }
 
-template <int P>
-struct AdjCellsPerBlock {
-  static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
-};
+template <int P, typename T, bool KAPPA, int DIR>
+__device__ __forceinline__ void adjoint_direction(const T* sge, const T* sue, const T* ske, const T* sgb,
+                                                  const T* sub, const T* skb, const T* __restrict__ g,
+                                                  const T* __restrict__ u, const T* __restrict__ kappa, uint32_t e,
+                                                  int le, int nvalid, int ecd, int nd, uint32_t estride, int ta,
+                                                  int tb, const ScalarArgs<T>& a, bool mass, T* og, T* ok) {
+  T v[P], uu[P], kv[P];
+  T gn[2][P], un[2][P], kn[2][P];
+  bool has[2];
+  lds_line<P, T, DIR>(sge, ta, tb, v);
+  lds_line<P, T, DIR>(sue, ta, tb, uu);
+  if (KAPPA) lds_line<P, T, DIR>(ske, ta, tb, kv);
+  neighbor_lines<P, T, DIR>(sgb, g, e, le, nvalid, ecd, nd, estride, ta, tb, gn, has);
+  neighbor_lines<P, T, DIR>(sub, u, e, le, nvalid, ecd, nd, estride, ta, tb, un, has);
+  if (KAPPA) neighbor_lines<P, T, DIR>(skb, kappa, e, le, nvalid, ecd, nd, estride, ta, tb, kn, has);
+  line_adjoint<P, T, KAPPA, DIR>(v, uu, kv, gn, un, kn, has, ta, tb, a, mass, og, ok);
+}
 
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
@@ -406,67 +453,102 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
                      T* __restrict__ ATg, T* __restrict__ dkappa, const ScalarArgs<T> a) {
   constexpr int EB = AdjCellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
-  __shared__ T sg[EB * N];
-  __shared__ T su[EB * N];
-  __shared__ T sk[KAPPA ? EB * N : 1];
-  __shared__ T sy0[EB * N], sy1[EB * N], sd0[EB * N], sd1[EB * N];
+  using Ly = Layout<P>;
+  __shared__ T sg[EB * Ly::NP];
+  __shared__ T su[EB * Ly::NP];
+  __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
+  __shared__ T sy0[EB * Ly::NP], sy1[EB * Ly::NP], sd0[EB * Ly::NP], sd1[EB * Ly::NP];
 
-  const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-  const int64_t ebase = (int64_t)blk * EB;
-  const int nvalid = (int)min((int64_t)EB, (int64_t)a.nelem - ebase);
-  for (int i = threadIdx.x; i < nvalid * N; i += NT) {
-    sg[i] = g[ebase * N + i];
-    su[i] = u[ebase * N + i];
-    if (KAPPA) sk[i] = kappa[ebase * N + i];
-  }
+  const BlockCoord bc = block_coord(xcd_swizzle(blockIdx.x, gridDim.x), a);
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int ex0 = bc.chunk * EB;
+  const int nvalid = min(EB, nx - ex0);
+  const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
+  const uint32_t gbase = (row + ex0) * N;
+  load_cells<P, T>(sg, g, gbase, nvalid, NT);
+  load_cells<P, T>(su, u, gbase, nvalid, NT);
+  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
   __syncthreads();
   const int le = threadIdx.x / L;
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
-  T outg2[P], outk2[P];
+  T og2[P], ok2[P];
   if (active) {
-    const int64_t e = ebase + le;
-    const int n0 = a.n[0], n1 = a.n[1];
-    const int ex = (int)(e % n0), ey = (int)((e / n0) % n1), ez = (int)(e / ((int64_t)n0 * n1));
-    const T* sge = sg + le * N;
-    const T* sue = su + le * N;
-    const T* ske = KAPPA ? sk + le * N : nullptr;
+    const int ex = ex0 + le;
+    const uint32_t e = row + ex;
+    const T* sge = sg + le * Ly::NP;
+    const T* sue = su + le * Ly::NP;
+    const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
     T og[P], ok[P];
-    line_adjoint<P, T, KAPPA, 0>(sge, sue, ske, ta * P + tb * L, ta, tb, e, ex, 1, g, u, kappa, a, true, og, ok);
+    adjoint_direction<P, T, KAPPA, 0>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, a,
+                                      true, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      sy0[le * N + ta * P + tb * L + i] = og[i];
-      sd0[le * N + ta * P + tb * L + i] = ok[i];
+      sy0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = og[i];
+      sd0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = ok[i];
     }
-    line_adjoint<P, T, KAPPA, 1>(sge, sue, ske, ta + tb * L, ta, tb, e, ey, n0, g, u, kappa, a, false, og, ok);
+    adjoint_direction<P, T, KAPPA, 1>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ey, ny,
+                                      (uint32_t)nx, ta, tb, a, false, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      sy1[le * N + ta + tb * L + i * P] = og[i];
-      sd1[le * N + ta + tb * L + i * P] = ok[i];
+      sy1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = og[i];
+      sd1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = ok[i];
     }
-    line_adjoint<P, T, KAPPA, 2>(sge, sue, ske, ta + tb * P, ta, tb, e, ez, (int64_t)n0 * n1, g, u, kappa, a,
-                                 false, outg2, outk2);
+    adjoint_direction<P, T, KAPPA, 2>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ez, nz,
+                                      (uint32_t)nx * ny, ta, tb, a, false, og2, ok2);
   }
   __syncthreads();
   if (active) {
-    const int64_t e = ebase + le;
-    const int off = ta + tb * P;
+    const uint32_t e = row + ex0 + le;
+    const int lo = le * Ly::NP + ta + Ly::S1 * tb;
+    const uint32_t go = e * N + ta + P * tb;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      const int idx = off + j * L;
-      ATg[e * N + idx] = sy0[le * N + idx] + sy1[le * N + idx] + outg2[j];
-      dkappa[e * N + idx] = sd0[le * N + idx] + sd1[le * N + idx] + outk2[j];
+      ATg[go + j * L] = sy0[lo + j * Ly::S2] + sy1[lo + j * Ly::S2] + og2[j];
+      dkappa[go + j * L] = sd0[lo + j * Ly::S2] + sd1[lo + j * Ly::S2] + ok2[j];
     }
   }
 }
 
+// b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
 template <int P, typename T>
-hipError_t launch_adjoint(const dg_mesh& M, const ScalarArgs<T>& a, const T* g, const T* u, const T* kappa, T* ATg,
-                          T* dk, hipStream_t s) {
+__global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const ScalarArgs<T> a, int64_t n) {
+  constexpr int N = P * P * P;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int l = (int)(i % N);
+  const int i0 = l % P, i1 = (l / P) % P, i2 = l / (P * P);
+  const T detJ = a.vs[0] / (a.hinv[0] * a.hinv[0]);  // |J| = vs_0 h_0^2
+  b[i] = (a.w[i0] * a.w[i1] * a.w[i2] * detJ) * f[i];
+}
+
+// Grid of the sweep: one block per x-chunk of eb cells of every (y, z) row.
+template <typename T>
+int64_t sweep_grid(ScalarArgs<T>& a, int eb) {
+  a.nchunk = (a.n[0] + eb - 1) / eb;
+  a.sz = a.n[2] >= 8 ? a.n[2] / 8 : 1;
+  return (int64_t)a.nchunk * a.n[1] * a.n[2];
+}
+
+template <int P, typename T>
+hipError_t launch_apply(const dg_mesh& M, ScalarArgs<T> a, const T* x, T* y, const T* kappa, hipStream_t s) {
+  constexpr int EB = CellsPerBlock<P>::value;
+  const int64_t G = sweep_grid(a, EB);
+  if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  if (kappa)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
+  else
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
+  return hipGetLastError();
+}
+
+template <int P, typename T>
+hipError_t launch_adjoint(const dg_mesh& M, ScalarArgs<T> a, const T* g, const T* u, const T* kappa, T* ATg, T* dk,
+                          hipStream_t s) {
   constexpr int EB = AdjCellsPerBlock<P>::value;
-  const int64_t G = (M.nelem + EB - 1) / EB;
-  if (G > 0x7fffffff) return hipErrorInvalidValue;
+  const int64_t G = sweep_grid(a, EB);
+  if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   if (kappa)
     hipLaunchKernelGGL((k_scalar_adjoint<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, g, u, kappa, ATg,
                        dk, a);
@@ -476,20 +558,49 @@ hipError_t launch_adjoint(const dg_mesh& M, const ScalarArgs<T>& a, const T* g, 
   return hipGetLastError();
 }
 
+#define DG_DISPATCH_P(P_, CALL)           \
+  switch (P_) {                           \
+    case 2: return CALL(2);               \
+    case 3: return CALL(3);               \
+    case 4: return CALL(4);               \
+    case 5: return CALL(5);               \
+    case 6: return CALL(6);               \
+    case 7: return CALL(7);               \
+    case 8: return CALL(8);               \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <typename T>
+hipError_t dispatch_apply(const dg_mesh& M, const ScalarArgs<T>& a, const T* x, T* y, const T* kappa,
+                          hipStream_t s) {
+#define DG_CALL(PP) launch_apply<PP, T>(M, a, x, y, kappa, s)
+  DG_DISPATCH_P(M.p, DG_CALL)
+#undef DG_CALL
+}
+
 template <typename T>
 hipError_t dispatch_adjoint(const dg_mesh& M, const ScalarArgs<T>& a, const T* g, const T* u, const T* kappa,
                             T* ATg, T* dk, hipStream_t s) {
+#define DG_CALL(PP) launch_adjoint<PP, T>(M, a, g, u, kappa, ATg, dk, s)
+  DG_DISPATCH_P(M.p, DG_CALL)
+#undef DG_CALL
+}
+
+template <typename T>
+hipError_t dispatch_load(const dg_mesh& M, const ScalarArgs<T>& a, const T* f, T* b, hipStream_t s) {
+  const int64_t n = M.ndofs;
+  const unsigned G = (unsigned)((n + 255) / 256);
   switch (M.p) {
-    case 2: return launch_adjoint<2, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 3: return launch_adjoint<3, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 4: return launch_adjoint<4, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 5: return launch_adjoint<5, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 6: return launch_adjoint<6, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 7: return launch_adjoint<7, T>(M, a, g, u, kappa, ATg, dk, s);
-    case 8: return launch_adjoint<8, T>(M, a, g, u, kappa, ATg, dk, s);
+#define DG_LOAD_CASE(PP) \
+  case PP: hipLaunchKernelGGL((k_scalar_load<PP, T>), dim3(G), dim3(256), 0, s, f, b, a, n); break;
+    DG_LOAD_CASE(2) DG_LOAD_CASE(3) DG_LOAD_CASE(4) DG_LOAD_CASE(5) DG_LOAD_CASE(6) DG_LOAD_CASE(7)
+    DG_LOAD_CASE(8)
+#undef DG_LOAD_CASE
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
 }
+
 }  // namespace
 
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa, bool transpose,
@@ -504,11 +615,6 @@ hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, cons
   return dispatch_apply<float>(M, a, (const float*)x, (float*)y, (const float*)kappa, s);
 }
 
-hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s) {
-  if (prec == DG_F64) return dispatch_load<double>(M, M.sd, (const double*)fq, (double*)b, s);
-  return dispatch_load<float>(M, M.sf, (const float*)fq, (float*)b, s);
-}
-
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa, void* ATg,
                           void* dkappa, hipStream_t s) {
   if (prec == DG_F64)
@@ -516,6 +622,11 @@ hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void*
                                     (double*)ATg, (double*)dkappa, s);
   return dispatch_adjoint<float>(M, M.sf, (const float*)g, (const float*)u, (const float*)kappa, (float*)ATg,
                                  (float*)dkappa, s);
+}
+
+hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s) {
+  if (prec == DG_F64) return dispatch_load<double>(M, M.sd, (const double*)fq, (double*)b, s);
+  return dispatch_load<float>(M, M.sf, (const float*)fq, (float*)b, s);
 }
 
 }  // namespace dgi

@@ -1,8 +1,241 @@
-// Matrix-free CG and FP32 iterative-refinement solver (placeholder).
-#include "internal.h"
+// Matrix-free solvers of the SIPG system A x = b (diffusion-reaction, theta = -1,
+// so A is symmetric positive definite): unpreconditioned CG in FP64, and
+// iterative refinement whose inner CG applies the FP32 operator.
+//
+// Refinement: r = b - A x in FP64 (FP64 apply), rhat = r / |r| rounded to FP32,
+// inner CG on A_32 d = rhat with FP32 vectors and FP64 inner products down to
+// |rhat - A_32 d| <= inner_rtol, then x += |r| d in FP64. Convergence is
+// declared on the true FP64 residual |b - A x| <= rtol |b| in both modes.
+#include <chrono>
+#include <cmath>
+#include <string>
 
-extern "C" dg_status dg_solve(const dg_mesh*, int, const double*, double*, const void*, const dg_solve_params*,
-                              dg_solve_info*, void*) {
-  dg_set_error("dg_solve is not built yet");
-  return DG_ERR_UNSUPPORTED;
+#include "solver.h"
+
+namespace {
+
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  ~HostPinned() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
+struct SolveError {
+  dg_status st;
+  std::string msg;
+};
+
+void ck(hipError_t e, const char* what) {
+  if (e != hipSuccess) throw SolveError{DG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+void dev_alloc(DevMem& m, size_t bytes) {
+  if (hipMalloc(&m.p, bytes > 0 ? bytes : 1) != hipSuccess) {
+    (void)hipGetLastError();
+    throw SolveError{DG_ERR_ALLOC, "device allocation failed"};
+  }
+}
+
+bool overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const char* pa = (const char*)a;
+  const char* pb = (const char*)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
+class Solver {
+ public:
+  Solver(const dg_mesh& M, const void* kappa, hipStream_t s) : M_(M), kappa_(kappa), s_(s), n_(M.ndofs) {
+    dev_alloc(partial_, sizeof(double) * dgi::RED_BLOCKS);
+    dev_alloc(state_, sizeof(dgi::CgState));
+    if (hipHostMalloc(&host_.p, sizeof(dgi::CgState)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw SolveError{DG_ERR_ALLOC, "pinned host allocation failed"};
+    }
+  }
+
+  dgi::CgState* st() { return (dgi::CgState*)state_.p; }
+  double* partial() { return (double*)partial_.p; }
+
+  dgi::CgState read() {
+    ck(hipMemcpyAsync(host_.p, state_.p, sizeof(dgi::CgState), hipMemcpyDeviceToHost, s_), "state readback");
+    ck(hipStreamSynchronize(s_), "hipStreamSynchronize");
+    return *(dgi::CgState*)host_.p;
+  }
+
+  void apply(int prec, const void* x, void* y, const void* kappa) {
+    ck(dgi::scalar_apply(M_, prec, x, y, kappa, false, s_), "apply");
+  }
+
+  // nrm2 = |b - A x|^2 with r = b - A x (q is scratch)
+  double true_residual(const double* b, const double* x, double* r, double* q) {
+    apply(DG_F64, x, q, kappa_);
+    ck(dgi::blas_residual(b, q, r, n_, partial(), st(), s_), "residual");
+    return read().nrm2;
+  }
+
+  // CG on A_prec z = rhs (r holds the initial residual rhs - A z, p a copy
+  // of it, st()->rr its square norm). Runs until sqrt(rr) <= tol or `budget`
+  // iterations; returns the iterations done.
+  int cg(int prec, void* z, void* r, void* p, void* q, const void* kappa, double tol, int budget, int check,
+         int* breakdown) {
+    int it = 0;
+    while (it < budget) {
+      if (it % check == 0) {
+        const dgi::CgState h = read();
+        if (h.breakdown) {
+          *breakdown = 1;
+          return it;
+        }
+        if (std::sqrt(h.rr) <= tol) return it;
+      }
+      apply(prec, p, q, kappa);
+      ck(dgi::blas_dot(p, q, prec, n_, partial(), st(), dgi::OP_ALPHA, s_), "p.Ap");
+      ck(dgi::blas_cg_update(z, r, p, q, prec, n_, partial(), st(), s_), "cg update");
+      ck(dgi::blas_xpay(r, p, prec, n_, st(), s_), "p update");
+      ++it;
+    }
+    const dgi::CgState h = read();
+    if (h.breakdown) *breakdown = 1;
+    return it;
+  }
+
+  int64_t n() const { return n_; }
+  hipStream_t stream() const { return s_; }
+
+ private:
+  const dg_mesh& M_;
+  const void* kappa_;
+  hipStream_t s_;
+  int64_t n_;
+  DevMem partial_, state_;
+  HostPinned host_;
+};
+
+dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa, const dg_solve_params* prm,
+              dg_solve_info* info, hipStream_t s) {
+  const auto t0 = std::chrono::steady_clock::now();
+  Solver S(*M, kappa, s);
+  const int64_t n = S.n();
+  const int check = prm->check_every > 0 ? prm->check_every : 10;
+  DevMem r, p, q;
+  dev_alloc(r, sizeof(double) * n);
+  dev_alloc(q, sizeof(double) * n);
+  ck(dgi::blas_dot(b, b, DG_F64, n, S.partial(), S.st(), dgi::OP_NORM, s), "b.b");
+  const double bnorm = std::sqrt(S.read().nrm2);
+  info->iterations = 0;
+  info->outer = 0;
+  dg_status status = DG_OK;
+  if (bnorm == 0.0) {
+    ck(hipMemsetAsync(x, 0, sizeof(double) * n, s), "zero x");
+    ck(hipStreamSynchronize(s), "hipStreamSynchronize");
+    info->rel_residual = 0.0;
+    return DG_OK;
+  }
+  const double target = prm->rtol * bnorm;
+  int breakdown = 0;
+  double res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+
+  if (mode == DG_SOLVE_CG_F64) {
+    dev_alloc(p, sizeof(double) * n);
+    int total = 0;
+    // restart from the true residual whenever the recursive one has converged but
+    // the true one has not (residual replacement)
+    while (res > target && total < prm->maxit && !breakdown) {
+      ck(dgi::blas_state_from_norm(S.st(), s), "state");
+      ck(dgi::blas_copy(r.p, p.p, DG_F64, n, s), "p = r");
+      total += S.cg(DG_F64, x, r.p, p.p, q.p, kappa, target, prm->maxit - total, check, &breakdown);
+      res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+    }
+    info->iterations = total;
+  } else {
+    DevMem rh, ph, qh, dh, k32;
+    dev_alloc(rh, sizeof(float) * n);
+    dev_alloc(ph, sizeof(float) * n);
+    dev_alloc(qh, sizeof(float) * n);
+    dev_alloc(dh, sizeof(float) * n);
+    const void* kap32 = nullptr;
+    if (kappa) {
+      dev_alloc(k32, sizeof(float) * M->nqp);
+      ck(dgi::blas_round_f32((const double*)kappa, (float*)k32.p, M->nqp, s), "kappa to FP32");
+      kap32 = k32.p;
+    }
+    int total = 0, outer = 0;
+    while (res > target && outer < prm->max_outer && total < prm->maxit && !breakdown) {
+      // S.true_residual left r = b - A x and nrm2 = |r|^2 on the device
+      ck(dgi::blas_ir_start((const double*)r.p, (float*)rh.p, (float*)ph.p, (float*)dh.p, n, S.st(), s), "ir start");
+      ck(dgi::blas_dot(rh.p, rh.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "rhat.rhat");
+      const double inner_tol = prm->inner_rtol * std::sqrt(S.read().rr0);
+      total += S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, kap32, inner_tol, prm->maxit - total, check, &breakdown);
+      // nrm2 still holds |r|^2 of this outer step
+      ck(dgi::blas_ir_correct(x, (const float*)dh.p, n, S.st(), s), "x += |r| d");
+      ++outer;
+      res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+    }
+    info->iterations = total;
+    info->outer = outer;
+  }
+  ck(hipStreamSynchronize(s), "hipStreamSynchronize");
+  info->rel_residual = res / bnorm;
+  info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (breakdown) {
+    dg_set_error("CG breakdown: p.Ap <= 0 or a non-finite value (is the operator SPD, theta = -1?)");
+    status = DG_BREAKDOWN;
+  } else if (res > target) {
+    dg_set_error("not converged within maxit / max_outer");
+    status = DG_NOT_CONVERGED;
+  }
+  return status;
+}
+
+}  // namespace
+
+extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa,
+                              const dg_solve_params* prm, dg_solve_info* info, void* stream) {
+  try {
+    if (!M || !b || !x || !prm || !info) {
+      dg_set_error("mesh, b, x, params and info must not be NULL");
+      return DG_ERR_ARG;
+    }
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC) {
+      dg_set_error("dg_solve is built for the diffusion-reaction operator");
+      return DG_ERR_UNSUPPORTED;
+    }
+    if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32) {
+      dg_set_error("unknown solve mode");
+      return DG_ERR_ARG;
+    }
+    if (!(prm->rtol > 0) || prm->maxit < 1 || (mode == DG_SOLVE_IR_F32 && (!(prm->inner_rtol > 0) || prm->max_outer < 1))) {
+      dg_set_error("rtol, inner_rtol must be > 0; maxit, max_outer >= 1");
+      return DG_ERR_ARG;
+    }
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    if (kap && !kappa) {
+      dg_set_error("kappa is required for kappa_mode DG_KAPPA_QP");
+      return DG_ERR_ARG;
+    }
+    const size_t nb = sizeof(double) * (size_t)M->ndofs;
+    if (((uintptr_t)b | (uintptr_t)x) % sizeof(double)) {
+      dg_set_error("b and x must be aligned to 8 bytes");
+      return DG_ERR_ARG;
+    }
+    if (overlap(b, nb, x, nb) || (kap && overlap(kappa, sizeof(double) * (size_t)M->nqp, x, nb))) {
+      dg_set_error("x overlaps b or kappa");
+      return DG_ERR_ARG;
+    }
+    return run(M, mode, b, x, kap ? kappa : nullptr, prm, info, (hipStream_t)stream);
+  } catch (const SolveError& e) {
+    dg_set_error(e.msg);
+    return e.st;
+  } catch (...) {
+    dg_set_error("dg_solve: unexpected exception");
+    return DG_ERR_DEVICE;
+  }
 }

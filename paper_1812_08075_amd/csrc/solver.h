@@ -1,0 +1,43 @@
+// Device state and vector kernels of the CG solvers.
+#pragma once
+
+#include "internal.h"
+
+namespace dgi {
+
+constexpr int RED_BLOCKS = 1024;  // fixed grid of the reductions (deterministic order)
+
+// CG scalars kept on the device; the host reads the record every few iterations.
+struct CgState {
+  double rr;      // r.r of the current residual
+  double rr0;     // r.r at the start of the run
+  double pq;      // p.Ap
+  double alpha;
+  double beta;
+  double nrm2;    // last norm computed with OP_NORM (outer residual of the refinement)
+  int32_t breakdown;
+  int32_t pad;
+};
+
+enum : int { OP_SET_RR = 0, OP_ALPHA = 1, OP_BETA = 2, OP_NORM = 3 };
+
+// a.b (FP64 accumulation) reduced into the state with `op`.
+hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* partial, CgState* st, int op,
+                    hipStream_t s);
+// x += alpha p, r -= alpha q, then beta = r.r / rr_old, rr = r.r.
+hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int prec, int64_t n, double* partial,
+                          CgState* st, hipStream_t s);
+hipError_t blas_xpay(const void* r, void* p, int prec, int64_t n, CgState* st, hipStream_t s);
+// r = b - Ax, nrm2 = r.r.
+hipError_t blas_residual(const double* b, const double* Ax, double* r, int64_t n, double* partial, CgState* st,
+                         hipStream_t s);
+// rhat = r/|r| (FP32), p = rhat, d = 0, rr = 1.
+hipError_t blas_ir_start(const double* r, float* rh, float* ph, float* d, int64_t n, CgState* st, hipStream_t s);
+// x += |r| d.
+hipError_t blas_ir_correct(double* x, const float* d, int64_t n, CgState* st, hipStream_t s);
+hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s);
+hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// rr = rr0 = nrm2, alpha = beta = 0.
+hipError_t blas_state_from_norm(CgState* st, hipStream_t s);
+
+}  // namespace dgi

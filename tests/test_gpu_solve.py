@@ -1,0 +1,121 @@
+"""GPU solver checks: FP64 CG and FP32-apply iterative refinement against the
+oracle (direct sparse solve and the oracle's own CG), failure reporting."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from oracle import Problem, ScalarDG, cg, problem_from_workload
+
+pytestmark = pytest.mark.gpu
+
+
+def setup(dg, w, n):
+    mesh = dg.Mesh(dg.desc_from_workload(w, n=n))
+    xyz = dg.dg_mesh_qpoints(mesh.handle)
+    fq = torch.from_numpy(workloads.sin_forcing(xyz, w.c)).cuda()
+    b = torch.empty(mesh.ndofs, dtype=torch.float64, device="cuda")
+    dg.dg_load_vector(mesh.handle, dg.DG_F64, fq, b)
+    return mesh, b
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_solve_matches_direct_solve(gpu_lib, mode):
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    n = 4
+    print(f"case: solve mode {mode} Q5 {n}^3", flush=True)
+    mesh, b = setup(dg, w, n)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=1e-10, inner_rtol=1e-5, maxit=20000)
+    assert st == dg.DG_OK, dg.lib.dg_last_error()
+    assert info.rel_residual <= 1e-10
+    A = ScalarDG(problem_from_workload(w, n=n)).assemble()
+    bh = b.cpu().numpy()
+    true_res = np.linalg.norm(bh - A.matvec(x.cpu().numpy())) / np.linalg.norm(bh)
+    assert true_res <= 1.05e-10
+    import scipy.sparse.linalg as spla
+    xd = spla.spsolve(A.to_scipy().tocsc(), bh)
+    err = np.linalg.norm(x.cpu().numpy() - xd) / np.linalg.norm(xd)
+    print(f"mode {mode}: its={info.iterations} outer={info.outer} res={info.rel_residual:.2e} |x-x_direct|={err:.2e}")
+    assert err < 1e-6
+    if mode == 1:
+        assert info.outer >= 2
+
+
+def test_cg_iterations_match_oracle_cg(gpu_lib):
+    """FP64 CG is the same iteration as the oracle's; counts agree closely."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    n = 3
+    mesh, b = setup(dg, w, n)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 0, b, x, rtol=1e-8, check_every=1)
+    A = ScalarDG(problem_from_workload(w, n=n)).assemble()
+    _, its, _ = cg(A.matvec, b.cpu().numpy(), rtol=1e-8)
+    assert st == dg.DG_OK
+    assert abs(info.iterations - its) <= max(3, its // 50), (info.iterations, its)
+
+
+def test_manufactured_solution_accuracy(gpu_lib):
+    """The solved sin solution is as accurate as the oracle's (L2 error by the oracle)."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    n = 4
+    mesh, b = setup(dg, w, n)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 1, b, x, rtol=1e-10)
+    assert st == dg.DG_OK
+    op = ScalarDG(problem_from_workload(w, n=n))
+    err = op.l2_error(x.cpu().numpy(), workloads.sin_solution)
+    import scipy.sparse.linalg as spla
+    ref = op.l2_error(spla.spsolve(op.assemble().to_scipy().tocsc(), b.cpu().numpy()), workloads.sin_solution)
+    assert abs(err - ref) <= 1e-6 * ref
+    assert err < 1e-4
+
+
+def test_kappa_solve(gpu_lib):
+    """kappa per point in the cells and kappa = 1 on faces (the trace reading can
+    extrapolate to negative face values, and then A need not be definite)."""
+    dg = gpu_lib
+    n, k = 3, 3
+    kap = workloads.lognormal(n ** 3 * 64, 3)
+    mesh = dg.Mesh(dg.make_desc(n, k=k, kappa_mode=dg.DG_KAPPA_QP, kappa_face=dg.DG_KAPPA_FACE_ONE))
+    b = torch.from_numpy(workloads.uniform(n ** 3 * 64, 4)).cuda()
+    kt = torch.from_numpy(kap).cuda()
+    for mode in (0, 1):
+        x = torch.zeros_like(b)
+        st, info = dg.dg_solve(mesh.handle, mode, b, x, kappa=kt, rtol=1e-10)
+        assert st == dg.DG_OK and info.rel_residual <= 1e-10
+        A = ScalarDG(Problem(n, n, n, k=k, kappa=kap, kappa_face_one=True)).assemble("explicit")
+        r = np.linalg.norm(b.cpu().numpy() - A.matvec(x.cpu().numpy())) / np.linalg.norm(b.cpu().numpy())
+        assert r <= 1.05e-10
+
+
+def test_not_converged_reported(gpu_lib):
+    dg = gpu_lib
+    mesh, b = setup(dg, workloads.WORKLOADS[5], 3)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 0, b, x, rtol=1e-10, maxit=5)
+    assert st == dg.DG_NOT_CONVERGED
+    assert info.iterations == 5 and info.rel_residual > 1e-10
+
+
+def test_breakdown_on_negative_definite_operator(gpu_lib):
+    """A large negative reaction coefficient makes A negative definite: the first
+    p.Ap is negative and CG reports a breakdown instead of iterating."""
+    dg = gpu_lib
+    mesh = dg.Mesh(dg.make_desc(3, k=2, c=-1e6))
+    b = torch.from_numpy(workloads.uniform(mesh.ndofs, 1)).cuda()
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 0, b, x, rtol=1e-10, maxit=100, check_every=1)
+    assert st == dg.DG_BREAKDOWN
+
+
+def test_zero_rhs(gpu_lib):
+    dg = gpu_lib
+    mesh = dg.Mesh(dg.make_desc(2, k=2))
+    b = torch.zeros(mesh.ndofs, dtype=torch.float64, device="cuda")
+    x = torch.ones_like(b)
+    st, info = dg.dg_solve(mesh.handle, 1, b, x)
+    assert st == dg.DG_OK and float(x.abs().max()) == 0.0
