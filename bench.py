@@ -142,22 +142,39 @@ def bench_solve(dg, rtol=1e-10):
     dg.dg_load_vector(mesh.handle, dg.DG_F64, fq, b)
     out = {}
     sol = {}
-    for name, mode in (("cg_f64", dg.DG_SOLVE_CG_F64), ("ir_f32", dg.DG_SOLVE_IR_F32)):
+    inner = {"cg_f64": 1e-5, "ir_f32": 1e-5, "ru_f32": 0.1}
+    for name, mode in (("cg_f64", dg.DG_SOLVE_CG_F64), ("ir_f32", dg.DG_SOLVE_IR_F32),
+                       ("ru_f32", dg.DG_SOLVE_RU_F32)):
         log(f"solve {name}")
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=rtol, inner_rtol=1e-5, maxit=200000,
+        st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=rtol, inner_rtol=inner[name], maxit=200000,
                                max_outer=20, check_every=20)
         el = time.perf_counter() - t0
         out[name] = {"status": st, "seconds": el, "iterations": info.iterations, "outer": info.outer,
                      "true_rel_residual": info.rel_residual}
         sol[name] = x
-    out["speedup_ir_over_cg"] = out["cg_f64"]["seconds"] / out["ir_f32"]["seconds"]
-    d = sol["ir_f32"] - sol["cg_f64"]
-    out["rel_diff_ir_vs_cg"] = float(torch.linalg.norm(d) / torch.linalg.norm(sol["cg_f64"]))
+    for name in ("ir_f32", "ru_f32"):
+        out[f"speedup_{name}_over_cg_f64"] = out["cg_f64"]["seconds"] / out[name]["seconds"]
+        d = sol[name] - sol["cg_f64"]
+        out[f"rel_diff_{name}_vs_cg_f64"] = float(torch.linalg.norm(d) / torch.linalg.norm(sol["cg_f64"]))
     out["workload"] = w.name
     return out
+
+
+def measured_traffic(kernel_file, key):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None
+    when the kernel source has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_1812_08075_amd", "csrc", kernel_file)
+    try:
+        rec = json.load(open(path))[key]
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except (OSError, KeyError, ValueError):
+        return None
+    return rec["traffic_bytes"] if rec.get("source_sha256_16") == sha else None
 
 
 def main():
@@ -168,6 +185,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--solve", action="store_true", help="include the Q5 solve comparison")
+    ap.add_argument("--only", choices=["stokes", "q4", "q5", "f32"], default=None,
+                    help="run one secondary workload only (for profiling), no JSON line")
     ap.add_argument("--copy-probe", action="store_true",
                     help="after the timed region, copy the 134 MB input vector 5 times with torch's copy "
                          "kernel (a known-size reference for HBM traffic counters)")
@@ -180,6 +199,17 @@ def main():
     import torch
     import paper_1812_08075_amd as dg
     import workloads
+
+    if args.only is not None:
+        w = {"stokes": workloads.WORKLOADS[3], "q4": workloads.WORKLOADS[4], "q5": workloads.WORKLOADS[5],
+             "f32": workloads.WORKLOADS[2]}[args.only]
+        prec = dg.DG_F32 if args.only == "f32" else dg.DG_F64
+        m, ms = bench_apply(dg, w, prec, args.steps, args.warmup)
+        log(f"{w.name}: {ms * 1e3:.1f} us per apply")
+        if args.only == "q4":
+            r = bench_adjoint(dg, w, args.steps, args.warmup)
+            log(f"{w.name} adjoint: {r['ms'] * 1e3:.1f} us")
+        return
 
     w2 = workloads.WORKLOADS[2]
     log(f"headline: {w2.name} FP64 apply, {args.steps} steps")
@@ -239,7 +269,8 @@ def main():
         "config": {"workload": w2.name, "k": w2.k, "m": w2.m, "mesh": f"{w2.n}^3", "ndofs": int(info.ndofs),
                    "penalty": "3k(k+1)/h", "theta": -1.0, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r64["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": r64["hbm_frac"], "traffic": None,
+                     "frac": r64["hbm_frac"],
+                     "traffic": measured_traffic("scalar_kernels.hip", "k_scalar_apply_q3_64cube_f64"),
                      "kernel": "k_scalar_apply<4,double,false>",
                      "algorithmic_bytes_per_launch": info.bytes_apply[0],
                      "fp64_flop_frac": r64["flop_frac"]},

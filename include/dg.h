@@ -64,7 +64,7 @@ enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
 enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
-enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1 };
+enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2 };
 
 /* Mesh and operator description (all fields are read by dg_mesh_create). */
 typedef struct {
@@ -102,7 +102,8 @@ typedef struct {
 
 typedef struct {
   double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual) */
-  double inner_rtol;        /* IR: relative residual target of each FP32 inner solve */
+  double inner_rtol;        /* IR: relative residual target of each FP32 inner solve;
+                               RU: residual drop between two corrections (0.1 if not in (0,1)) */
   int32_t maxit;            /* CG: iterations; IR: total inner iterations */
   int32_t max_outer;        /* IR: refinement steps */
   int32_t check_every;      /* read the residual norm to the host every n iterations */
@@ -110,7 +111,7 @@ typedef struct {
 
 typedef struct {
   int32_t iterations;       /* CG iterations (FP64 CG) or total inner iterations (IR) */
-  int32_t outer;            /* IR refinement steps (0 for FP64 CG) */
+  int32_t outer;            /* refinement steps / residual replacements (0 for FP64 CG) */
   double rel_residual;      /* true ||b - A x||_2 / ||b||_2 in FP64 at exit */
   double seconds;           /* wall time of the solve, host clock */
 } dg_solve_info;
@@ -141,9 +142,17 @@ dg_status dg_apply_adjoint(const dg_mesh* mesh, int precision, const void* g, co
                            const void* kappa, void* ATg, void* dkappa, void* stream);
 
 /* Solves A x = b (diffusion-reaction, theta = -1, so A is SPD) by
- * unpreconditioned CG. DG_SOLVE_CG_F64: FP64 throughout. DG_SOLVE_IR_F32:
- * iterative refinement, outer residual b - A x in FP64, inner CG on the
- * FP32 operator with FP64 inner products, FP64 solution update.
+ * unpreconditioned CG. Convergence is always judged on the true FP64
+ * residual ||b - A x||_2 <= rtol ||b||_2.
+ *  DG_SOLVE_CG_F64: FP64 throughout.
+ *  DG_SOLVE_IR_F32: classic iterative refinement: outer residual b - A x in
+ *    FP64, a fresh inner CG on the FP32 operator (FP32 vectors, FP64 inner
+ *    products) to inner_rtol, FP64 solution update.
+ *  DG_SOLVE_RU_F32: refinement that keeps the inner Krylov space: one FP32
+ *    CG runs throughout; whenever its residual has dropped by inner_rtol
+ *    since the last correction (checked every check_every iterations), the FP32
+ *    iterate is added to x in FP64, the residual is replaced by the true
+ *    FP64 b - A x and the search direction is kept.
  * b, x: device FP64 vectors; x holds the initial guess on entry. kappa as in
  * dg_apply (FP64 values; the FP32 operator rounds them). Synchronous. */
 dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,

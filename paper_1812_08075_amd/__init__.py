@@ -24,7 +24,7 @@ DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES = 0, 1
 DG_F64, DG_F32 = 0, 1
 DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
 DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
-DG_SOLVE_CG_F64, DG_SOLVE_IR_F32 = 0, 1
+DG_SOLVE_CG_F64, DG_SOLVE_IR_F32, DG_SOLVE_RU_F32 = 0, 1, 2
 
 _DTYPE = {DG_F64: torch.float64, DG_F32: torch.float32}
 
@@ -199,7 +199,7 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value:
+        if h is not None and h.value and lib is not None:
             lib.dg_mesh_destroy(h)
             self.handle = None
 

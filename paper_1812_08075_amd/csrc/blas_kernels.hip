@@ -128,6 +128,19 @@ __global__ void __launch_bounds__(RT) k_ir_correct(double* __restrict__ x, const
     x[i] = fma(s, (double)d[i], x[i]);
 }
 
+// x += (FP64) xl; xl = 0 (the FP32 iterate of the refinement moves into x)
+__global__ void __launch_bounds__(RT) k_accumulate(double* __restrict__ x, float* __restrict__ xl, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    x[i] += (double)xl[i];
+    xl[i] = 0.0f;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(RT) k_fill(T* __restrict__ a, T v, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) a[i] = v;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(RT) k_copy(const T* __restrict__ a, T* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) b[i] = a[i];
@@ -146,6 +159,15 @@ __global__ void k_state_reset(CgState* st, int from_norm) {
     st->rr0 = rr;
     st->alpha = st->beta = st->pq = 0.0;
     st->breakdown = 0;
+  }
+}
+
+// Zeroes every field of a freshly allocated state record.
+__global__ void k_state_zero(CgState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->rr = st->rr0 = st->pq = st->alpha = st->beta = st->nrm2 = 0.0;
+    st->breakdown = 0;
+    st->pad = 0;
   }
 }
 
@@ -207,6 +229,19 @@ hipError_t blas_ir_correct(double* x, const float* d, int64_t n, CgState* st, hi
   return hipGetLastError();
 }
 
+hipError_t blas_accumulate(double* x, float* xl, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_accumulate, dim3(grid_for(n)), dim3(RT), 0, s, x, xl, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_zero(void* a, int prec, int64_t n, hipStream_t s) {
+  if (prec == DG_F64)
+    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n)), dim3(RT), 0, s, (double*)a, 0.0, n);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n)), dim3(RT), 0, s, (float*)a, 0.0f, n);
+  return hipGetLastError();
+}
+
 hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s) {
   if (prec == DG_F64)
     hipLaunchKernelGGL(k_copy<double>, dim3(grid_for(n)), dim3(RT), 0, s, (const double*)a, (double*)b, n);
@@ -217,6 +252,11 @@ hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s)
 
 hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_round_f32, dim3(grid_for(n)), dim3(RT), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_state_zero(CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_zero, dim3(1), dim3(1), 0, s, st);
   return hipGetLastError();
 }
 

@@ -115,6 +115,21 @@ void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
   a.nelem = (int32_t)M.nelem;
   a.mask = M.desc.dirichlet_mask;
   a.kappa_face_one = M.desc.kappa_face == DG_KAPPA_FACE_ONE;
+  for (int d = 0; d < 3; ++d) {
+    const double vsd = detJ / (h[d] * h[d]);
+    for (int q = 0; q < p; ++q)
+      for (int j = 0; j < p; ++j) a.Dv[d][q * p + j] = (T)(vsd * t.wq[q] * t.D[q][j]);
+    for (int s = 0; s < 2; ++s) {
+      const double sg = s ? 1.0 : -1.0;
+      for (int j = 0; j < p; ++j) {
+        a.dno[d][s][j] = (T)(sg / h[d] * t.de[s][j]);
+        a.dni[d][s][j] = (T)(-sg / h[d] * t.de[1 - s][j]);
+      }
+    }
+    a.fG[d] = (T)(detJ / h[d] * coef / h[d]);
+  }
+  for (int i = 0; i < p; ++i) a.cw[i] = (T)(M.desc.c * detJ * t.wq[i]);
+  dgi::derive_face_constants(a);
 }
 
 size_t elem_size(int prec) { return prec == DG_F64 ? sizeof(double) : sizeof(float); }
@@ -139,6 +154,17 @@ hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 }  // namespace
 
 void dg_set_error(const std::string& msg) { g_last_error = msg; }
+
+template <typename T>
+void dgi::derive_face_constants(ScalarArgs<T>& a) {
+  for (int d = 0; d < 3; ++d) {
+    const double fs = (double)a.fs[d], hi = (double)a.hinv[d];
+    a.fA[d] = (T)(fs * 0.5 * (double)a.c_cons);
+    for (int s = 0; s < 2; ++s) a.fB[d][s] = (T)(fs * 0.5 * (double)a.c_sym * (s ? 1.0 : -1.0) * hi);
+  }
+}
+template void dgi::derive_face_constants<double>(ScalarArgs<double>&);
+template void dgi::derive_face_constants<float>(ScalarArgs<float>&);
 
 // The host-side trilinear geometry used by the Stokes setup and dg_mesh_qpoints.
 namespace dgi {

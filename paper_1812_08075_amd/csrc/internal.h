@@ -53,6 +53,15 @@ struct ScalarArgs {
   // blocks are swept as (slab of sz z-planes, y, z within the slab, chunk)
   int32_t nchunk;      // chunks per x-row
   int32_t sz;          // z-planes per slab
+  // Per-direction tables with the constant factors folded in; a line's
+  // tangential weight w_a w_b multiplies its whole result once at the end.
+  T Dv[3][PMAX * PMAX];  // (|J|/h_d^2) w_q l_j'(x_q): contraction to the points plus quadrature scaling
+  T dno[3][2][PMAX];     // (2s-1)/h_d l_j'(s): outward normal derivative of the own trace at side s
+  T dni[3][2][PMAX];     // -(2s-1)/h_d l_j'(1-s): the neighbour's outward normal derivative there
+  T cw[PMAX];            // c |J| w_i: mass term
+  T fA[3];               // |F_d| c_cons / 2
+  T fG[3];               // |F_d| gamma_d
+  T fB[3][2];            // |F_d| c_sym / 2 (2s-1)/h_d
 };
 
 // Kernel arguments of the Stokes kernels (general trilinear geometry).
@@ -91,6 +100,9 @@ namespace dgi {
 // Launchers (defined next to their kernels). They return the launch status.
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa,
                         bool transpose, hipStream_t s);
+// Recomputes the face constants fA, fB of the folded tables from c_cons, c_sym.
+template <typename T>
+void derive_face_constants(ScalarArgs<T>& a);
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa,
                           void* ATg, void* dkappa, hipStream_t s);
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s);

@@ -122,51 +122,42 @@ __device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restric
   }
 }
 
-// Volume and face work of one 1D line of one cell in direction DIR.
+// Volume and face work of one 1D line of one cell in direction DIR, without
+// the line's tangential quadrature weight w_a w_b, which the caller applies once.
 //  v, kv: the line's values and kappa at its nodes; nb[s], nk[s]: the
 //  neighbour's matching line across side s (unused when !has_nb[s]);
-//  (ta, tb): tangential node indices (tensor weights); mass: add c w |J| u.
+//  mass: add the c |J| w u term (once per cell, on the x lines).
 template <int P, typename T, bool KAPPA, int DIR>
 __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
-                                           const bool* has_nb, int ta, int tb, const ScalarArgs<T>& a, bool mass,
-                                           T* out) {
-  const T wt = a.w[ta] * a.w[tb];
-  // cell: r_q = kappa_q w_q |J|/h^2 (D v)_q, out = D^T r
+                                           const bool* has_nb, const ScalarArgs<T>& a, bool mass, T* out) {
+  // cell: r_q = kappa_q (|J|/h^2) w_q (D v)_q (contraction to the points and
+  // quadrature scaling in one table), out = D^T r
   T r[P];
-  const T vsw = a.vs[DIR] * wt;
 #pragma unroll
   for (int q = 0; q < P; ++q) {
     T du = T(0);
 #pragma unroll
-    for (int j = 0; j < P; ++j) du = fma(a.D[q * P + j], v[j], du);
-    const T sc = vsw * a.w[q];
-    r[q] = KAPPA ? (sc * kv[q]) * du : sc * du;
+    for (int j = 0; j < P; ++j) du = fma(a.Dv[DIR][q * P + j], v[j], du);
+    r[q] = KAPPA ? kv[q] * du : du;
   }
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    T s = T(0);
+    T s = mass ? a.cw[i] * v[i] : T(0);
 #pragma unroll
     for (int q = 0; q < P; ++q) s = fma(a.D[q * P + i], r[q], s);
     out[i] = s;
   }
-  if (mass) {
-    const T cw = a.cmass * wt;
-#pragma unroll
-    for (int i = 0; i < P; ++i) out[i] = fma(cw * a.w[i], v[i], out[i]);
-  }
   // faces at both ends of the line
-  const T fw = wt * a.fs[DIR];
-  const T hi = a.hinv[DIR];
   const bool face_kappa = KAPPA && !a.kappa_face_one;
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
     if (!has_nb[s] && !dirichlet) continue;
-    T uT = T(0), dT = T(0);
+    T uT = T(0), dnuT = T(0);  // own trace and outward normal derivative
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       uT = fma(a.e[s][j], v[j], uT);
-      dT = fma(a.de[s][j], v[j], dT);
+      dnuT = fma(a.dno[DIR][s][j], v[j], dnuT);
     }
     T kT = T(1);
     if (face_kappa) {
@@ -174,15 +165,13 @@ __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb
 #pragma unroll
       for (int j = 0; j < P; ++j) kT = fma(a.e[s][j], kv[j], kT);
     }
-    const T sg = s ? T(1) : T(-1);  // outward normal = sg * e_DIR
-    const T dnuT = sg * hi * dT;    // outward normal derivative of the own trace
     T Rv, Rdv;
     if (has_nb[s]) {
-      T uN = T(0), dN = T(0);
+      T uN = T(0), dnuN = T(0);  // neighbour's trace and its own outward normal derivative
 #pragma unroll
       for (int j = 0; j < P; ++j) {
         uN = fma(a.e[1 - s][j], nb[s][j], uN);
-        dN = fma(a.de[1 - s][j], nb[s][j], dN);
+        dnuN = fma(a.dni[DIR][s][j], nb[s][j], dnuN);
       }
       T kN = T(1);
       if (face_kappa) {
@@ -190,16 +179,13 @@ __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb
 #pragma unroll
         for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], nk[s][j], kN);
       }
-      const T dnuN = -sg * hi * dN;  // the neighbour's outward normal is opposite
       const T jump = uT - uN;
-      Rv = T(0.5) * a.c_cons * (kT * dnuT - kN * dnuN) + a.gam[DIR] * jump;
-      Rdv = T(0.5) * a.c_sym * kT * jump;
+      Rv = fma(a.fA[DIR], kT * dnuT - kN * dnuN, a.fG[DIR] * jump);
+      Rdv = a.fB[DIR][s] * (kT * jump);
     } else {
-      Rv = a.c_cons * kT * dnuT + a.gam[DIR] * uT;
-      Rdv = a.c_sym * kT * uT;
+      Rv = fma(T(2) * a.fA[DIR], kT * dnuT, a.fG[DIR] * uT);
+      Rdv = T(2) * a.fB[DIR][s] * (kT * uT);
     }
-    Rv *= fw;
-    Rdv *= fw * sg * hi;
 #pragma unroll
     for (int i = 0; i < P; ++i) out[i] = fma(Rv, a.e[s][i], fma(Rdv, a.de[s][i], out[i]));
   }
@@ -261,8 +247,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   using Ly = Layout<P>;
   __shared__ T sx[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
-  __shared__ T sy0[EB * Ly::NP];
-  __shared__ T sy1[EB * Ly::NP];
+  __shared__ T sy[EB * Ly::NP];  // x-line results, then += y-line results
 
   const BlockCoord bc = block_coord(xcd_swizzle(blockIdx.x, gridDim.x), a);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -278,13 +263,14 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
-  T out2[P];
+  const T wt = a.w[ta] * a.w[tb];  // tangential weight of this thread's lines
+  const int ex = ex0 + le;
+  const uint32_t e = row + ex;
+  const T* sxe = sx + le * Ly::NP;
+  const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
+  T out0[P], out1[P], out2[P];
   if (active) {
-    const int ex = ex0 + le;
-    const uint32_t e = row + ex;
-    const T* sxe = sx + le * Ly::NP;
-    const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
-    T v[P], kv[P], out[P];
+    T v[P], kv[P];
     T nb[2][P], nk[2][P];
     bool has[2];
     // lines along x: (i1, i2) = (ta, tb)
@@ -292,32 +278,40 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     if (KAPPA) lds_line<P, T, 0>(ske, ta, tb, kv);
     neighbor_lines<P, T, 0>(sx, x, e, le, nvalid, ex, nx, 1u, ta, tb, nb, has);
     if (KAPPA) neighbor_lines<P, T, 0>(sk, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 0>(v, kv, nb, nk, has, ta, tb, a, true, out);
-#pragma unroll
-    for (int i = 0; i < P; ++i) sy0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = out[i];
+    line_apply<P, T, KAPPA, 0>(v, kv, nb, nk, has, a, true, out0);
     // lines along y: (i0, i2) = (ta, tb)
     lds_line<P, T, 1>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
     neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb, has);
     if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 1>(v, kv, nb, nk, has, ta, tb, a, false, out);
+    line_apply<P, T, KAPPA, 1>(v, kv, nb, nk, has, a, false, out1);
 #pragma unroll
-    for (int i = 0; i < P; ++i) sy1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = out[i];
+    for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
+  }
+  __syncthreads();
+  if (active) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      T* yi = sy + le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
+      *yi = fma(wt, out1[i], *yi);
+    }
     // lines along z: (i0, i1) = (ta, tb), kept in registers
+    T v[P], kv[P];
+    T nb[2][P], nk[2][P];
+    bool has[2];
     lds_line<P, T, 2>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
     const uint32_t nxy = (uint32_t)nx * ny;
     neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb, has);
     if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 2>(v, kv, nb, nk, has, ta, tb, a, false, out2);
+    line_apply<P, T, KAPPA, 2>(v, kv, nb, nk, has, a, false, out2);
   }
   __syncthreads();
   if (active) {
-    const uint32_t e = row + ex0 + le;
     const int lo = le * Ly::NP + ta + Ly::S1 * tb;
     T* __restrict__ ye = y + e * N + ta + P * tb;
 #pragma unroll
-    for (int j = 0; j < P; ++j) ye[j * L] = sy0[lo + j * Ly::S2] + sy1[lo + j * Ly::S2] + out2[j];
+    for (int j = 0; j < P; ++j) ye[j * L] = fma(wt, out2[j], sy[lo + j * Ly::S2]);
   }
 }
 
@@ -607,11 +601,17 @@ hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, cons
                         hipStream_t s) {
   if (prec == DG_F64) {
     ScalarArgs<double> a = M.sd;
-    if (transpose) std::swap(a.c_cons, a.c_sym);
+    if (transpose) {
+      std::swap(a.c_cons, a.c_sym);
+      derive_face_constants(a);
+    }
     return dispatch_apply<double>(M, a, (const double*)x, (double*)y, (const double*)kappa, s);
   }
   ScalarArgs<float> a = M.sf;
-  if (transpose) std::swap(a.c_cons, a.c_sym);
+  if (transpose) {
+    std::swap(a.c_cons, a.c_sym);
+    derive_face_constants(a);
+  }
   return dispatch_apply<float>(M, a, (const float*)x, (float*)y, (const float*)kappa, s);
 }
 

@@ -1,11 +1,22 @@
 // Matrix-free solvers of the SIPG system A x = b (diffusion-reaction, theta = -1,
-// so A is symmetric positive definite): unpreconditioned CG in FP64, and
-// iterative refinement whose inner CG applies the FP32 operator.
+// so A is symmetric positive definite): unpreconditioned CG in FP64, and two
+// refinement schemes whose CG applies the FP32 operator.
 //
-// Refinement: r = b - A x in FP64 (FP64 apply), rhat = r / |r| rounded to FP32,
-// inner CG on A_32 d = rhat with FP32 vectors and FP64 inner products down to
-// |rhat - A_32 d| <= inner_rtol, then x += |r| d in FP64. Convergence is
-// declared on the true FP64 residual |b - A x| <= rtol |b| in both modes.
+// Classic refinement (DG_SOLVE_IR_F32): r = b - A x in FP64 (FP64 apply),
+// rhat = r / |r| rounded to FP32, a fresh inner CG on A_32 d = rhat with FP32
+// vectors and FP64 inner products down to |rhat - A_32 d| <= inner_rtol, then
+// x += |r| d in FP64.
+//
+// Refinement keeping the Krylov space (DG_SOLVE_RU_F32): one FP32 CG runs
+// throughout on the correction; each time its recursive residual has dropped
+// by the factor inner_rtol (0.1 by default) since the last correction, its
+// iterate is added to x in FP64 and its
+// residual is replaced by the true FP64 b - A x (rounded to FP32) while the
+// search direction is kept, so the convergence of the Krylov space is not
+// restarted.
+//
+// Convergence is declared on the true FP64 residual |b - A x| <= rtol |b| in
+// every mode.
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -59,6 +70,7 @@ class Solver {
       (void)hipGetLastError();
       throw SolveError{DG_ERR_ALLOC, "pinned host allocation failed"};
     }
+    ck(dgi::blas_state_zero(st(), s_), "state init");
   }
 
   dgi::CgState* st() { return (dgi::CgState*)state_.p; }
@@ -155,6 +167,62 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
     }
     info->iterations = total;
+  } else if (mode == DG_SOLVE_RU_F32) {
+    // one FP32 CG whose residual is replaced by the true FP64 residual (and its
+    // iterate moved into x) each time it has dropped by RU_DROP since the last
+    // replacement; the search direction is kept across replacements
+    const double RU_DROP = (prm->inner_rtol > 0.0 && prm->inner_rtol < 1.0) ? prm->inner_rtol : 0.1;
+    DevMem rl, pl, ql, xl, k32;
+    dev_alloc(rl, sizeof(float) * n);
+    dev_alloc(pl, sizeof(float) * n);
+    dev_alloc(ql, sizeof(float) * n);
+    dev_alloc(xl, sizeof(float) * n);
+    const void* kap32 = nullptr;
+    if (kappa) {
+      dev_alloc(k32, sizeof(float) * M->nqp);
+      ck(dgi::blas_round_f32((const double*)kappa, (float*)k32.p, M->nqp, s), "kappa to FP32");
+      kap32 = k32.p;
+    }
+    ck(dgi::blas_zero(xl.p, DG_F32, n, s), "xl = 0");
+    ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
+    ck(dgi::blas_copy(rl.p, pl.p, DG_F32, n, s), "p = r");
+    ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
+    double last = std::sqrt(S.read().rr);
+    int total = 0, outer = 0, since_restart = 0;
+    while (res > target && total < prm->maxit && !breakdown) {
+      for (int it = 0; it < check && total < prm->maxit; ++it, ++total, ++since_restart) {
+        S.apply(DG_F32, pl.p, ql.p, kap32);
+        ck(dgi::blas_dot(pl.p, ql.p, DG_F32, n, S.partial(), S.st(), dgi::OP_ALPHA, s), "p.Ap");
+        ck(dgi::blas_cg_update(xl.p, rl.p, pl.p, ql.p, DG_F32, n, S.partial(), S.st(), s), "cg update");
+        ck(dgi::blas_xpay(rl.p, pl.p, DG_F32, n, S.st(), s), "p update");
+      }
+      const dgi::CgState h = S.read();
+      // A non-positive p.Ap in the FP32 recursion (its residual has drifted below
+      // FP32 accuracy) triggers a correction with a fresh search direction; a
+      // breakdown right after such a restart is a real one.
+      const bool lost = h.breakdown != 0;
+      if (lost && since_restart <= check) {
+        breakdown = 1;
+        break;
+      }
+      const double cur = std::sqrt(h.rr);
+      if (lost || cur <= RU_DROP * last || cur <= target || total >= prm->maxit) {
+        ck(dgi::blas_accumulate(x, (float*)xl.p, n, s), "x += xl");
+        ++outer;
+        res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+        if (res <= target) break;
+        ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
+        if (lost) {
+          ck(dgi::blas_state_zero(S.st(), s), "state reset");
+          ck(dgi::blas_copy(rl.p, pl.p, DG_F32, n, s), "p = r");
+          since_restart = 0;
+        }
+        ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
+        last = std::sqrt(S.read().rr);
+      }
+    }
+    info->iterations = total;
+    info->outer = outer;
   } else {
     DevMem rh, ph, qh, dh, k32;
     dev_alloc(rh, sizeof(float) * n);
@@ -173,11 +241,17 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       ck(dgi::blas_ir_start((const double*)r.p, (float*)rh.p, (float*)ph.p, (float*)dh.p, n, S.st(), s), "ir start");
       ck(dgi::blas_dot(rh.p, rh.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "rhat.rhat");
       const double inner_tol = prm->inner_rtol * std::sqrt(S.read().rr0);
-      total += S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, kap32, inner_tol, prm->maxit - total, check, &breakdown);
+      int inner_lost = 0;
+      const int its = S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, kap32, inner_tol, prm->maxit - total, check, &inner_lost);
+      total += its;
       // nrm2 still holds |r|^2 of this outer step
       ck(dgi::blas_ir_correct(x, (const float*)dh.p, n, S.st(), s), "x += |r| d");
       ++outer;
+      const double prev = res;
       res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+      // an inner breakdown (FP32 rounding) just ends that inner solve; it is a
+      // real breakdown only when the correction made no progress
+      if (inner_lost && !(res < prev)) breakdown = 1;
     }
     info->iterations = total;
     info->outer = outer;
@@ -208,7 +282,7 @@ extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, doubl
       dg_set_error("dg_solve is built for the diffusion-reaction operator");
       return DG_ERR_UNSUPPORTED;
     }
-    if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32) {
+    if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32 && mode != DG_SOLVE_RU_F32) {
       dg_set_error("unknown solve mode");
       return DG_ERR_ARG;
     }

@@ -36,7 +36,12 @@ hipError_t blas_ir_start(const double* r, float* rh, float* ph, float* d, int64_
 // x += |r| d.
 hipError_t blas_ir_correct(double* x, const float* d, int64_t n, CgState* st, hipStream_t s);
 hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s);
+// x += xl (FP32 to FP64), xl = 0.
+hipError_t blas_accumulate(double* x, float* xl, int64_t n, hipStream_t s);
+hipError_t blas_zero(void* a, int prec, int64_t n, hipStream_t s);
 hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// every field zero (a fresh state record).
+hipError_t blas_state_zero(CgState* st, hipStream_t s);
 // rr = rr0 = nrm2, alpha = beta = 0.
 hipError_t blas_state_from_norm(CgState* st, hipStream_t s);
 

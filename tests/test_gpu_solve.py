@@ -19,7 +19,7 @@ def setup(dg, w, n):
     return mesh, b
 
 
-@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1, 2])
 def test_solve_matches_direct_solve(gpu_lib, mode):
     dg = gpu_lib
     w = workloads.WORKLOADS[5]
@@ -27,7 +27,8 @@ def test_solve_matches_direct_solve(gpu_lib, mode):
     print(f"case: solve mode {mode} Q5 {n}^3", flush=True)
     mesh, b = setup(dg, w, n)
     x = torch.zeros_like(b)
-    st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=1e-10, inner_rtol=1e-5, maxit=20000)
+    inner = 0.1 if mode == 2 else 1e-5
+    st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=1e-10, inner_rtol=inner, maxit=20000)
     assert st == dg.DG_OK, dg.lib.dg_last_error()
     assert info.rel_residual <= 1e-10
     A = ScalarDG(problem_from_workload(w, n=n)).assemble()
@@ -39,7 +40,7 @@ def test_solve_matches_direct_solve(gpu_lib, mode):
     err = np.linalg.norm(x.cpu().numpy() - xd) / np.linalg.norm(xd)
     print(f"mode {mode}: its={info.iterations} outer={info.outer} res={info.rel_residual:.2e} |x-x_direct|={err:.2e}")
     assert err < 1e-6
-    if mode == 1:
+    if mode in (1, 2):
         assert info.outer >= 2
 
 
@@ -83,13 +84,24 @@ def test_kappa_solve(gpu_lib):
     mesh = dg.Mesh(dg.make_desc(n, k=k, kappa_mode=dg.DG_KAPPA_QP, kappa_face=dg.DG_KAPPA_FACE_ONE))
     b = torch.from_numpy(workloads.uniform(n ** 3 * 64, 4)).cuda()
     kt = torch.from_numpy(kap).cuda()
-    for mode in (0, 1):
+    for mode in (0, 1, 2):
         x = torch.zeros_like(b)
         st, info = dg.dg_solve(mesh.handle, mode, b, x, kappa=kt, rtol=1e-10)
         assert st == dg.DG_OK and info.rel_residual <= 1e-10
         A = ScalarDG(Problem(n, n, n, k=k, kappa=kap, kappa_face_one=True)).assemble("explicit")
         r = np.linalg.norm(b.cpu().numpy() - A.matvec(x.cpu().numpy())) / np.linalg.norm(b.cpu().numpy())
         assert r <= 1.05e-10
+
+
+@pytest.mark.parametrize("drop", [1e-2, 1e-5])
+def test_refinement_survives_fp32_breakdown(gpu_lib, drop):
+    """Driving the FP32 recursion far below FP32 accuracy makes p.Ap non-positive;
+    the refinement restarts from the true residual instead of failing."""
+    dg = gpu_lib
+    mesh, b = setup(dg, workloads.WORKLOADS[5], 4)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 2, b, x, rtol=1e-10, inner_rtol=drop, maxit=50000, check_every=50)
+    assert st == dg.DG_OK and info.rel_residual <= 1e-10
 
 
 def test_not_converged_reported(gpu_lib):
