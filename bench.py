@@ -46,6 +46,25 @@ def time_applies(fn, steps, warmup, stream):
     return start.elapsed_time(end) / steps
 
 
+def copy_reference():
+    """Achieved HBM bandwidth of a plain device copy of 8 x 134 MB (torch's copy
+    kernel), timed like the applies: the same-box reference for the fractions."""
+    import torch
+    n = 16777216
+    src = [torch.ones(n, dtype=torch.float64, device="cuda") for _ in range(4)]
+    dst = [torch.empty_like(src[0]) for _ in range(4)]
+    stream = torch.cuda.current_stream()
+    it = [0]
+
+    def step():
+        i = it[0] % 4
+        it[0] += 1
+        dst[i].copy_(src[i])
+
+    ms = time_applies(step, 40, 4, stream)
+    return {"ms": round(ms, 5), "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+
+
 def rates(info, ms, prec, nbytes=None, flops=None):
     t = ms * 1e-3
     b = info.bytes_apply[prec] if nbytes is None else nbytes
@@ -223,7 +242,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    extra = {"apply_q3_f64_warm": r64}
+    extra = {"apply_q3_f64_warm": r64, "hbm_copy_reference": copy_reference()}
 
     if not args.no_extra:
         log("Q3 FP64 cold (4 rotating buffer pairs)")

@@ -103,7 +103,7 @@ typedef struct {
 typedef struct {
   double rtol;              /* stop when ||b - A x||_2 <= rtol ||b||_2 (true FP64 residual) */
   double inner_rtol;        /* IR: relative residual target of each FP32 inner solve;
-                               RU: residual drop between two corrections (0.1 if not in (0,1)) */
+                               RU: residual drop between two corrections (0.1 unless in [1e-3, 1)) */
   int32_t maxit;            /* CG: iterations; IR: total inner iterations */
   int32_t max_outer;        /* IR: refinement steps */
   int32_t check_every;      /* read the residual norm to the host every n iterations */

@@ -49,11 +49,18 @@ __global__ void __launch_bounds__(RT) k_finalize(const double* __restrict__ part
       st->rr = s;
       st->rr0 = s;
       break;
-    case OP_ALPHA:
+    case OP_ALPHA: {
       st->pq = s;
-      if (!(s > 0.0) || !isfinite(s)) st->breakdown = 1;
-      st->alpha = (s > 0.0) ? st->rr / s : 0.0;
+      const double alpha = (s > 0.0) ? st->rr / s : 0.0;
+      // non-positive or non-finite p.Ap, or a step that would overflow FP32 vectors
+      if (!(s > 0.0) || !isfinite(s) || !(alpha < 1e30)) {
+        st->breakdown = 1;
+        st->alpha = 0.0;
+      } else {
+        st->alpha = alpha;
+      }
       break;
+    }
     case OP_BETA:
       st->beta = (st->rr > 0.0) ? s / st->rr : 0.0;
       st->rr = s;

@@ -93,6 +93,8 @@ struct dg_mesh {
   std::vector<double> vertices;   // host copy (perturbed meshes)
   double* d_vertices = nullptr;   // device copy
   double* d_gamma = nullptr;      // per-face penalties [3][faces of direction d]
+  double* d_wline = nullptr;      // w_a w_b of line a + p b (p^2 entries), FP64
+  float* f_wline = nullptr;       // the same in FP32
   int64_t gamma_off[3] = {0, 0, 0};
 };
 

@@ -241,7 +241,7 @@ __device__ __forceinline__ void neighbor_lines(const T* __restrict__ s, const T*
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
-                   const ScalarArgs<T> a) {
+                   const T* __restrict__ wline, const ScalarArgs<T> a) {
   constexpr int EB = CellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
@@ -255,17 +255,28 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const int nvalid = min(EB, nx - ex0);
   const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
   const uint32_t gbase = (row + ex0) * N;
-  load_cells<P, T>(sx, x, gbase, nvalid, NT);
-  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
-  __syncthreads();
-
   const int le = threadIdx.x / L;
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
-  const T wt = a.w[ta] * a.w[tb];  // tangential weight of this thread's lines
   const int ex = ex0 + le;
   const uint32_t e = row + ex;
+  const uint32_t nxy = (uint32_t)nx * ny;
+  // the y- and z-neighbour lines come from global memory (L2) and do not depend
+  // on the LDS stage: issue them together with the cell loads
+  T nb1[2][P], nk1[2][P], nb2[2][P], nk2[2][P];
+  bool has1[2], has2[2];
+  if (active) {
+    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb1, has1);
+    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk1, has1);
+    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb2, has2);
+    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk2, has2);
+  }
+  load_cells<P, T>(sx, x, gbase, nvalid, NT);
+  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
+  __syncthreads();
+
+  const T wt = wline[li];  // tangential weight w_ta w_tb of this thread's lines
   const T* sxe = sx + le * Ly::NP;
   const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
   T out0[P], out1[P], out2[P];
@@ -282,9 +293,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     // lines along y: (i0, i2) = (ta, tb)
     lds_line<P, T, 1>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
-    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb, has);
-    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 1>(v, kv, nb, nk, has, a, false, out1);
+    line_apply<P, T, KAPPA, 1>(v, kv, nb1, nk1, has1, a, false, out1);
 #pragma unroll
     for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
   }
@@ -297,14 +306,9 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     }
     // lines along z: (i0, i1) = (ta, tb), kept in registers
     T v[P], kv[P];
-    T nb[2][P], nk[2][P];
-    bool has[2];
     lds_line<P, T, 2>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
-    const uint32_t nxy = (uint32_t)nx * ny;
-    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb, has);
-    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 2>(v, kv, nb, nk, has, a, false, out2);
+    line_apply<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
   }
   __syncthreads();
   if (active) {
@@ -329,11 +333,10 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
 // (c_cons = -1, c_sym = theta; on Dirichlet sides without the 1/2 and N).
 template <int P, typename T, bool KAPPA, int DIR>
 __device__ __forceinline__ void line_adjoint(const T* v, const T* uu, const T* kv, const T (*gn)[P],
-                                             const T (*un)[P], const T (*kn)[P], const bool* has_nb, int ta,
-                                             int tb, const ScalarArgs<T>& a, bool mass, T* outg, T* outk) {
+                                             const T (*un)[P], const T (*kn)[P], const bool* has_nb, T wt,
+                                             const ScalarArgs<T>& a, bool mass, T* outg, T* outk) {
   const T cf_cons = a.c_cons, cf_sym = a.c_sym;  // forward coefficients
   const T ca_cons = a.c_sym, ca_sym = a.c_cons;  // transposed apply
-  const T wt = a.w[ta] * a.w[tb];
   const T vsw = a.vs[DIR] * wt;
   T r[P];
 #pragma unroll
@@ -428,7 +431,7 @@ __device__ __forceinline__ void adjoint_direction(const T* sge, const T* sue, co
                                                   const T* sub, const T* skb, const T* __restrict__ g,
                                                   const T* __restrict__ u, const T* __restrict__ kappa, uint32_t e,
                                                   int le, int nvalid, int ecd, int nd, uint32_t estride, int ta,
-                                                  int tb, const ScalarArgs<T>& a, bool mass, T* og, T* ok) {
+                                                  int tb, T wt, const ScalarArgs<T>& a, bool mass, T* og, T* ok) {
   T v[P], uu[P], kv[P];
   T gn[2][P], un[2][P], kn[2][P];
   bool has[2];
@@ -438,13 +441,14 @@ __device__ __forceinline__ void adjoint_direction(const T* sge, const T* sue, co
   neighbor_lines<P, T, DIR>(sgb, g, e, le, nvalid, ecd, nd, estride, ta, tb, gn, has);
   neighbor_lines<P, T, DIR>(sub, u, e, le, nvalid, ecd, nd, estride, ta, tb, un, has);
   if (KAPPA) neighbor_lines<P, T, DIR>(skb, kappa, e, le, nvalid, ecd, nd, estride, ta, tb, kn, has);
-  line_adjoint<P, T, KAPPA, DIR>(v, uu, kv, gn, un, kn, has, ta, tb, a, mass, og, ok);
+  line_adjoint<P, T, KAPPA, DIR>(v, uu, kv, gn, un, kn, has, wt, a, mass, og, ok);
 }
 
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
     k_scalar_adjoint(const T* __restrict__ g, const T* __restrict__ u, const T* __restrict__ kappa,
-                     T* __restrict__ ATg, T* __restrict__ dkappa, const ScalarArgs<T> a) {
+                     T* __restrict__ ATg, T* __restrict__ dkappa, const T* __restrict__ wline,
+                     const ScalarArgs<T> a) {
   constexpr int EB = AdjCellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
@@ -467,6 +471,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
+  const T wt = wline[li];
   T og2[P], ok2[P];
   if (active) {
     const int ex = ex0 + le;
@@ -475,22 +480,22 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
     const T* sue = su + le * Ly::NP;
     const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
     T og[P], ok[P];
-    adjoint_direction<P, T, KAPPA, 0>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, a,
-                                      true, og, ok);
+    adjoint_direction<P, T, KAPPA, 0>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, wt,
+                                      a, true, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       sy0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = og[i];
       sd0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = ok[i];
     }
     adjoint_direction<P, T, KAPPA, 1>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ey, ny,
-                                      (uint32_t)nx, ta, tb, a, false, og, ok);
+                                      (uint32_t)nx, ta, tb, wt, a, false, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
       sy1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = og[i];
       sd1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = ok[i];
     }
     adjoint_direction<P, T, KAPPA, 2>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ez, nz,
-                                      (uint32_t)nx * ny, ta, tb, a, false, og2, ok2);
+                                      (uint32_t)nx * ny, ta, tb, wt, a, false, og2, ok2);
   }
   __syncthreads();
   if (active) {
@@ -525,15 +530,23 @@ int64_t sweep_grid(ScalarArgs<T>& a, int eb) {
   return (int64_t)a.nchunk * a.n[1] * a.n[2];
 }
 
+template <typename T>
+const T* line_weights(const dg_mesh& M);
+template <>
+const double* line_weights<double>(const dg_mesh& M) { return M.d_wline; }
+template <>
+const float* line_weights<float>(const dg_mesh& M) { return M.f_wline; }
+
 template <int P, typename T>
 hipError_t launch_apply(const dg_mesh& M, ScalarArgs<T> a, const T* x, T* y, const T* kappa, hipStream_t s) {
   constexpr int EB = CellsPerBlock<P>::value;
   const int64_t G = sweep_grid(a, EB);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const T* wl = line_weights<T>(M);
   if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, wl, a);
   else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, a);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, wl, a);
   return hipGetLastError();
 }
 
@@ -543,12 +556,13 @@ hipError_t launch_adjoint(const dg_mesh& M, ScalarArgs<T> a, const T* g, const T
   constexpr int EB = AdjCellsPerBlock<P>::value;
   const int64_t G = sweep_grid(a, EB);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const T* wl = line_weights<T>(M);
   if (kappa)
     hipLaunchKernelGGL((k_scalar_adjoint<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, g, u, kappa, ATg,
-                       dk, a);
+                       dk, wl, a);
   else
     hipLaunchKernelGGL((k_scalar_adjoint<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, g, u, kappa,
-                       ATg, dk, a);
+                       ATg, dk, wl, a);
   return hipGetLastError();
 }
 

@@ -9,7 +9,7 @@
 //
 // Refinement keeping the Krylov space (DG_SOLVE_RU_F32): one FP32 CG runs
 // throughout on the correction; each time its recursive residual has dropped
-// by the factor inner_rtol (0.1 by default) since the last correction, its
+// by the factor inner_rtol (in [1e-3, 1), else 0.1) since the last correction, its
 // iterate is added to x in FP64 and its
 // residual is replaced by the true FP64 b - A x (rounded to FP32) while the
 // search direction is kept, so the convergence of the Krylov space is not
@@ -171,7 +171,8 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     // one FP32 CG whose residual is replaced by the true FP64 residual (and its
     // iterate moved into x) each time it has dropped by RU_DROP since the last
     // replacement; the search direction is kept across replacements
-    const double RU_DROP = (prm->inner_rtol > 0.0 && prm->inner_rtol < 1.0) ? prm->inner_rtol : 0.1;
+    // below ~1e-3 per correction the FP32 recursion would run past FP32 accuracy
+    const double RU_DROP = (prm->inner_rtol >= 1e-3 && prm->inner_rtol < 1.0) ? prm->inner_rtol : 0.1;
     DevMem rl, pl, ql, xl, k32;
     dev_alloc(rl, sizeof(float) * n);
     dev_alloc(pl, sizeof(float) * n);
@@ -257,6 +258,7 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     info->outer = outer;
   }
   ck(hipStreamSynchronize(s), "hipStreamSynchronize");
+  if (!std::isfinite(res)) breakdown = 1;  // never report a NaN/Inf residual as converged
   info->rel_residual = res / bnorm;
   info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   if (breakdown) {

@@ -101,6 +101,26 @@ __device__ __forceinline__ void load_corners(const StokesGeom& g, const StokesAr
   }
 }
 
+// Component c of the vector whose d-th entry is vd and whose two other entries,
+// in increasing index order, are va and vb (selects; no indexed register arrays).
+template <typename V>
+__device__ __forceinline__ V place(int d, int c, V vd, V va, V vb) {
+  if (c == 0) return d == 0 ? vd : va;
+  if (c == 1) return d == 0 ? va : (d == 1 ? vd : vb);
+  return d == 2 ? vd : vb;
+}
+
+// Index of pressure node (jd along d, ja along t1, jb along t2) in the cell block.
+template <int KP>
+__device__ __forceinline__ int pnode(int d, int jd, int ja, int jb) {
+  return place(d, 0, jd, ja, jb) + KP * (place(d, 1, jd, ja, jb) + KP * place(d, 2, jd, ja, jb));
+}
+
+__device__ __forceinline__ void face_dirs(int d, int& t1, int& t2) {
+  t1 = d == 0 ? 1 : 0;
+  t2 = d == 2 ? 1 : 2;
+}
+
 template <int P>
 __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ x, double* __restrict__ y,
                                                      const StokesArgs a, const StokesGeom geo) {
@@ -108,43 +128,278 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
   constexpr int N = P * P * P, NQ = KP * KP * KP, L = P * P;
   constexpr int NB = 3 * N + NQ;      // DOFs per cell
   constexpr int NF = 6 * L;           // face points of the cell
+  constexpr int RA = (6 * NF > 10 * N) ? 6 * NF : 10 * N;
+  // staging of the pressure contractions: cell stages s1 [P KP^2], s2 [P^2 KP] and
+  // face-trace stages c1 [12 KP^2], c2 [12 P KP] live side by side; the test
+  // stages (KP P^2 + 6 KP P + KP^2 P + 6 KP^2) reuse the space later
+  constexpr int TMP = P * KP * KP + P * P * KP + 12 * KP * KP + 12 * P * KP;
+  static_assert(KP * P * P + 6 * KP * P + KP * KP * P + 6 * KP * KP <= TMP, "pressure staging");
   __shared__ double su[3 * N];        // velocity
   __shared__ double sp[NQ];           // pressure
   __shared__ double sX[24];           // own corners
   __shared__ double nX[6][24];        // neighbour corners
-  __shared__ double np_[6][NQ];       // neighbour pressure
-  __shared__ double sG[9 * N];        // reference gradients G[c*3+a][i]
-  __shared__ double sR[9 * N];        // cell residual coefficients of d_a v_c
-  __shared__ double sRp[N];           // cell residual coefficient of q
-  __shared__ double fUN[3][NF];       // neighbour velocity traces
-  __shared__ double fDN[3][NF];       // neighbour normal reference derivatives
-  __shared__ double fV[3][NF];        // face coefficients of v_c
-  __shared__ double fG[9][NF];        // face coefficients of d_a v_c
+  __shared__ double npr[6][NQ];       // neighbour pressure
+  __shared__ double spq[N];           // pressure at the quadrature points
+  __shared__ double fpT[NF], fpN[NF]; // pressure traces (own, neighbour) at the face points
+  __shared__ double regA[RA];         // faces: velocity traces fT[3][NF], fN[3][NF]; then cell residual sR[9][N], sRp[N]
+  __shared__ double fV[3 * NF];       // face coefficients of v_c
+  __shared__ double fRg[3 * NF];      // face coefficients of grad v_c . nu
+  __shared__ double fJn[3 * NF];      // J^{-1} nu at the face points
   __shared__ double fQ[NF];           // face coefficients of q
+  __shared__ double tmp[TMP];
+  double* fT = regA;
+  double* fN = regA + 3 * NF;
+  double* sR = regA;
+  double* sRp = regA + 9 * N;
 
   const int t = threadIdx.x;
   const int e = blockIdx.x;
-  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int nx = a.n[0], ny = a.n[1];
   const int ec[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
   const int64_t base = (int64_t)e * NB;
   const int64_t estr[3] = {1, nx, (int64_t)nx * ny};
+  unsigned hasn = 0;  // bit f: face f has a neighbour
+#pragma unroll
+  for (int f = 0; f < 6; ++f) {
+    const int d = f >> 1, s = f & 1;
+    const int c = ec[d] + (s ? 1 : -1);
+    if (c >= 0 && c < a.n[d]) hasn |= 1u << f;
+  }
+  auto has_nb_of = [&](int f) { return ((hasn >> f) & 1u) != 0; };
+  // runtime-direction helpers (selects instead of indexed register arrays)
+  auto ecd = [&](int d) { return d == 0 ? ec[0] : (d == 1 ? ec[1] : ec[2]); };
+  auto estrd = [&](int d) { return d == 0 ? estr[0] : (d == 1 ? estr[1] : estr[2]); };
 
   // ---- loads ---------------------------------------------------------------
   for (int i = t; i < 3 * N; i += NT) su[i] = x[base + i];
   for (int i = t; i < NQ; i += NT) sp[i] = x[base + 3 * N + i];
   load_corners(geo, a, ec[0], ec[1], ec[2], sX, t);
+#pragma unroll
   for (int f = 0; f < 6; ++f) {
+    if (!has_nb_of(f)) continue;
     const int d = f >> 1, s = f & 1;
     int nc[3] = {ec[0], ec[1], ec[2]};
     nc[d] += s ? 1 : -1;
-    if (nc[d] < 0 || nc[d] >= a.n[d]) continue;
     load_corners(geo, a, nc[0], nc[1], nc[2], nX[f], t);
     const int64_t nb = (int64_t)e + (s ? estr[d] : -estr[d]);
-    for (int i = t; i < NQ; i += NT) np_[f][i] = x[nb * NB + 3 * N + i];
+    for (int i = t; i < NQ; i += NT) npr[f][i] = x[nb * NB + 3 * N + i];
   }
   __syncthreads();
 
-  // ---- volume, pointwise --------------------------------------------------
+  // ---- pressure by sum factorization: at the points, and face traces -------
+  // cell: (A_p x A_p x A_p) P, one direction per stage
+  double* s1 = tmp;              // [q0][j1][j2]
+  double* s2 = tmp + P * KP * KP; // [q0][q1][j2]
+  for (int i = t; i < P * KP * KP; i += NT) {
+    const int q0 = i % P, j12 = i / P;
+    double v = 0;
+#pragma unroll
+    for (int j0 = 0; j0 < KP; ++j0) v = fma(a.Ap[q0 * KP + j0], sp[j0 + KP * j12], v);
+    s1[i] = v;
+  }
+  // faces, stage 1: contract the normal direction with e_p(side) (own: side s, neighbour: 1 - s)
+  double* c1 = tmp + P * KP * KP + P * P * KP;  // [12][ja][jb]
+  for (int i = t; i < 12 * KP * KP; i += NT) {
+    const int fo = i / (KP * KP), r = i - fo * KP * KP;
+    const int f = fo >> 1, o = fo & 1;  // o: 0 own, 1 neighbour
+    const int d = f >> 1, s = f & 1;
+    const int ja = r % KP, jb = r / KP;
+    double v = 0;
+    if (o == 0 || has_nb_of(f)) {
+      const double* P_ = o ? npr[f] : sp;
+      const int side = o ? 1 - s : s;
+#pragma unroll
+      for (int jd = 0; jd < KP; ++jd) v = fma(a.ep[side][jd], P_[pnode<KP>(d, jd, ja, jb)], v);
+    }
+    c1[i] = v;
+  }
+  __syncthreads();
+  for (int i = t; i < P * P * KP; i += NT) {
+    const int q0 = i % P, q1 = (i / P) % P, j2 = i / (P * P);
+    double v = 0;
+#pragma unroll
+    for (int j1 = 0; j1 < KP; ++j1) v = fma(a.Ap[q1 * KP + j1], s1[q0 + P * (j1 + KP * j2)], v);
+    s2[i] = v;
+  }
+  double* c2 = c1 + 12 * KP * KP;  // [12][pa][jb]
+  for (int i = t; i < 12 * P * KP; i += NT) {
+    const int fo = i / (P * KP), r = i - fo * P * KP;
+    const int pa = r % P, jb = r / P;
+    double v = 0;
+#pragma unroll
+    for (int ja = 0; ja < KP; ++ja) v = fma(a.Ap[pa * KP + ja], c1[fo * KP * KP + ja + KP * jb], v);
+    c2[i] = v;
+  }
+  __syncthreads();
+  for (int i = t; i < N; i += NT) {
+    const int q01 = i % (P * P), q2 = i / (P * P);
+    double v = 0;
+#pragma unroll
+    for (int j2 = 0; j2 < KP; ++j2) v = fma(a.Ap[q2 * KP + j2], s2[q01 + P * P * j2], v);
+    spq[i] = v;
+  }
+  for (int i = t; i < 12 * L; i += NT) {
+    const int fo = i / L, pt = i - fo * L;
+    const int pa = pt % P, pb = pt / P;
+    double v = 0;
+#pragma unroll
+    for (int jb = 0; jb < KP; ++jb) v = fma(a.Ap[pb * KP + jb], c2[fo * P * KP + pa + P * jb], v);
+    const int f = fo >> 1, o = fo & 1;
+    (o ? fpN : fpT)[f * L + pt] = v;
+  }
+
+  // ---- faces, phase 1: velocity traces and normal derivatives --------------
+  double dnT[2][3], dnN[2][3];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int fp = t + NT * r;
+    if (fp >= NF) continue;
+    const int f = fp / L, pt = fp - f * L;
+    const int d = f >> 1, s = f & 1;
+    const int pa = pt % P, pb = pt / P;
+    const int off = d == 0 ? P * pa + L * pb : (d == 1 ? pa + L * pb : pa + P * pb);
+    const int str = d == 0 ? 1 : (d == 1 ? P : L);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double u = 0, dn = 0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const double v = su[c * N + off + j * str];
+        u = fma(a.e[s][j], v, u);
+        dn = fma(a.de[s][j], v, dn);
+      }
+      fT[c * NF + fp] = u;
+      dnT[r][c] = dn;
+    }
+    if (has_nb_of(f)) {
+      const int64_t nb = (int64_t)e + (s ? estrd(d) : -estrd(d));
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double u = 0, dn = 0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          const double v = x[nb * NB + c * N + off + j * str];
+          u = fma(a.e[1 - s][j], v, u);
+          dn = fma(a.de[1 - s][j], v, dn);
+        }
+        fN[c * NF + fp] = u;
+        dnN[r][c] = dn;
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fN[c * NF + fp] = 0.0;
+        dnN[r][c] = 0.0;
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- faces, phase 2: flux at every face point ---------------------------
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    const int fp = t + NT * r;
+    if (fp >= NF) continue;
+    const int f = fp / L, pt = fp - f * L;
+    const int d = f >> 1, s = f & 1;
+    const int pa = pt % P, pb = pt / P;
+    const bool has_nb = has_nb_of(f);
+    const bool dir = (a.mask >> f) & 1u;
+    if (!has_nb && !dir) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        fV[c * NF + fp] = 0.0;
+        fRg[c * NF + fp] = 0.0;
+        fJn[c * NF + fp] = 0.0;
+      }
+      fQ[fp] = 0.0;
+      continue;
+    }
+    const int fb = f * L;
+    // geometry at the face point from the own cell
+    const double xs = (double)s, xa = a.xq[pa], xb = a.xq[pb];
+    const double xi[3] = {place(d, 0, xs, xa, xb), place(d, 1, xs, xa, xb), place(d, 2, xs, xa, xb)};
+    double J[3][3], Ji[3][3];
+    jacobian(sX, xi, J);
+    const double det = invert(J, Ji);
+    // row d of J^{-1} (the gradient of xi_d): normal direction
+    double rn[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) rn[k] = d == 0 ? Ji[0][k] : (d == 1 ? Ji[1][k] : Ji[2][k]);
+    const double nn = sqrt(rn[0] * rn[0] + rn[1] * rn[1] + rn[2] * rn[2]);
+    const double sg = s ? 1.0 : -1.0;
+    const double nu[3] = {sg * rn[0] / nn, sg * rn[1] / nn, sg * rn[2] / nn};
+    const double dA = fabs(det) * nn * a.w[pa] * a.w[pb];
+    const double Jn[3] = {Ji[0][0] * nu[0] + Ji[0][1] * nu[1] + Ji[0][2] * nu[2],
+                          Ji[1][0] * nu[0] + Ji[1][1] * nu[1] + Ji[1][2] * nu[2],
+                          Ji[2][0] * nu[0] + Ji[2][1] * nu[1] + Ji[2][2] * nu[2]};
+    // own full reference gradient along nu: normal part from phase 1, tangential
+    // parts by D across the face points of the own trace
+    double uT[3], gradT_n[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double ga = 0, gb = 0;
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        ga = fma(a.D[pa * P + j], fT[c * NF + fb + j + P * pb], ga);
+        gb = fma(a.D[pb * P + j], fT[c * NF + fb + pa + P * j], gb);
+      }
+      const double dn = dnT[r][c];
+      gradT_n[c] = Jn[0] * place(d, 0, dn, ga, gb) + Jn[1] * place(d, 1, dn, ga, gb) + Jn[2] * place(d, 2, dn, ga, gb);
+      uT[c] = fT[c * NF + fp];
+    }
+    const double pT = fpT[fp];
+    const int ct1 = d == 0 ? ec[1] : ec[0], ct2 = d == 2 ? ec[1] : ec[2];
+    const int nd = d == 0 ? a.n[0] : (d == 1 ? a.n[1] : a.n[2]);
+    const int nt1 = d == 0 ? a.n[1] : a.n[0];
+    const int64_t goff = d == 0 ? geo.goff[0] : (d == 1 ? geo.goff[1] : geo.goff[2]);
+    const double gam = geo.gamma[goff + (ecd(d) + s) + (int64_t)(nd + 1) * (ct1 + (int64_t)nt1 * ct2)];
+    double Rv[3], Rg[3], Rq = 0.0;
+    if (has_nb) {
+      const double xn[3] = {place(d, 0, 1.0 - xs, xa, xb), place(d, 1, 1.0 - xs, xa, xb),
+                            place(d, 2, 1.0 - xs, xa, xb)};
+      double JN[3][3], JiN[3][3];
+      jacobian(nX[f], xn, JN);
+      invert(JN, JiN);
+      const double JnN[3] = {JiN[0][0] * nu[0] + JiN[0][1] * nu[1] + JiN[0][2] * nu[2],
+                             JiN[1][0] * nu[0] + JiN[1][1] * nu[1] + JiN[1][2] * nu[2],
+                             JiN[2][0] * nu[0] + JiN[2][1] * nu[1] + JiN[2][2] * nu[2]};
+      const double pN = fpN[fp];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        double ga = 0, gb = 0;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+          ga = fma(a.D[pa * P + j], fN[c * NF + fb + j + P * pb], ga);
+          gb = fma(a.D[pb * P + j], fN[c * NF + fb + pa + P * j], gb);
+        }
+        const double dn = dnN[r][c];
+        const double gradN_n = JnN[0] * place(d, 0, dn, ga, gb) + JnN[1] * place(d, 1, dn, ga, gb) +
+                               JnN[2] * place(d, 2, dn, ga, gb);
+        const double jump = uT[c] - fN[c * NF + fp];
+        Rv[c] = dA * (-0.5 * (gradT_n[c] + gradN_n) + gam * jump + 0.5 * (pT + pN) * nu[c]);
+        Rg[c] = dA * 0.5 * a.theta * jump;
+        Rq += dA * 0.5 * jump * nu[c];
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        Rv[c] = dA * (-gradT_n[c] + gam * uT[c] + pT * nu[c]);
+        Rg[c] = dA * a.theta * uT[c];
+        Rq += dA * uT[c] * nu[c];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      fV[c * NF + fp] = Rv[c];
+      fRg[c * NF + fp] = Rg[c];
+      fJn[c * NF + fp] = Jn[c];
+    }
+    fQ[fp] = Rq;
+  }
+  __syncthreads();
+
+  // ---- cell terms at the points (Algorithm 1, parts 1 and 2) ---------------
   for (int i = t; i < N; i += NT) {
     const int i0 = i % P, i1 = (i / P) % P, i2 = i / L;
     double g[3][3];
@@ -161,19 +416,8 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
       g[c][0] = g0;
       g[c][1] = g1;
       g[c][2] = g2;
-      sG[(3 * c + 0) * N + i] = g0;
-      sG[(3 * c + 1) * N + i] = g1;
-      sG[(3 * c + 2) * N + i] = g2;
     }
-    double pq = 0.0;
-#pragma unroll
-    for (int j2 = 0; j2 < KP; ++j2)
-#pragma unroll
-      for (int j1 = 0; j1 < KP; ++j1) {
-        const double w12 = a.Ap[i1 * KP + j1] * a.Ap[i2 * KP + j2];
-#pragma unroll
-        for (int j0 = 0; j0 < KP; ++j0) pq = fma(a.Ap[i0 * KP + j0] * w12, sp[j0 + KP * (j1 + KP * j2)], pq);
-      }
+    const double pq = spq[i];
     const double xi[3] = {a.xq[i0], a.xq[i1], a.xq[i2]};
     double J[3][3], Ji[3][3];
     jacobian(sX, xi, J);
@@ -192,182 +436,6 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
             wd * (Ji[aa][0] * gp[0] + Ji[aa][1] * gp[1] + Ji[aa][2] * gp[2] - pq * Ji[aa][c]);
     }
     sRp[i] = -wd * div;
-  }
-
-  // ---- faces, phase 1: neighbour traces ----------------------------------
-  for (int fp = t; fp < NF; fp += NT) {
-    const int f = fp / L, pt = fp - f * L;
-    const int d = f >> 1, s = f & 1;
-    int nc[3] = {ec[0], ec[1], ec[2]};
-    nc[d] += s ? 1 : -1;
-    if (nc[d] < 0 || nc[d] >= a.n[d]) continue;
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const int pa = pt % P, pb = pt / P;
-    int off = 0, str = 1;
-    {
-      int idx[3];
-      idx[t1] = pa;
-      idx[t2] = pb;
-      idx[d] = 0;
-      off = idx[0] + P * idx[1] + L * idx[2];
-      str = d == 0 ? 1 : (d == 1 ? P : L);
-    }
-    const int64_t nb = (int64_t)e + (s ? estr[d] : -estr[d]);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double uN = 0, dN = 0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const double v = x[nb * NB + c * N + off + j * str];
-        uN = fma(a.e[1 - s][j], v, uN);
-        dN = fma(a.de[1 - s][j], v, dN);
-      }
-      fUN[c][fp] = uN;
-      fDN[c][fp] = dN;
-    }
-  }
-  __syncthreads();
-
-  // ---- faces, phase 2: flux at every face point ---------------------------
-  for (int fp = t; fp < NF; fp += NT) {
-    const int f = fp / L, pt = fp - f * L;
-    const int d = f >> 1, s = f & 1;
-    int nc[3] = {ec[0], ec[1], ec[2]};
-    nc[d] += s ? 1 : -1;
-    const bool has_nb = nc[d] >= 0 && nc[d] < a.n[d];
-    const bool dir = (a.mask >> f) & 1u;
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    const int pa = pt % P, pb = pt / P;
-    if (!has_nb && !dir) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        fV[c][fp] = 0.0;
-        for (int aa = 0; aa < 3; ++aa) fG[3 * c + aa][fp] = 0.0;
-      }
-      fQ[fp] = 0.0;
-      continue;
-    }
-    int idx[3];
-    idx[t1] = pa;
-    idx[t2] = pb;
-    idx[d] = 0;
-    const int off = idx[0] + P * idx[1] + L * idx[2];
-    const int str = d == 0 ? 1 : (d == 1 ? P : L);
-    // own traces of u_c and of all reference derivatives
-    double uT[3], gT[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double u = 0, dn = 0, ga = 0, gb = 0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        const int node = off + j * str;
-        u = fma(a.e[s][j], su[c * N + node], u);
-        dn = fma(a.de[s][j], su[c * N + node], dn);
-        ga = fma(a.e[s][j], sG[(3 * c + t1) * N + node], ga);
-        gb = fma(a.e[s][j], sG[(3 * c + t2) * N + node], gb);
-      }
-      uT[c] = u;
-      gT[c][d] = dn;
-      gT[c][t1] = ga;
-      gT[c][t2] = gb;
-    }
-    // own pressure trace: e_p(s) along d, A_p at the tangential nodes
-    double pT = 0.0;
-#pragma unroll
-    for (int jd = 0; jd < KP; ++jd)
-#pragma unroll
-      for (int ja = 0; ja < KP; ++ja)
-#pragma unroll
-        for (int jb = 0; jb < KP; ++jb) {
-          int pj[3];
-          pj[d] = jd;
-          pj[t1] = ja;
-          pj[t2] = jb;
-          pT = fma(a.ep[s][jd] * a.Ap[pa * KP + ja] * a.Ap[pb * KP + jb], sp[pj[0] + KP * (pj[1] + KP * pj[2])], pT);
-        }
-    // geometry from the own cell: normal (outward) and area element
-    double xi[3];
-    xi[d] = (double)s;
-    xi[t1] = a.xq[pa];
-    xi[t2] = a.xq[pb];
-    double J[3][3], Ji[3][3];
-    jacobian(sX, xi, J);
-    const double det = invert(J, Ji);
-    const double nn = sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
-    const double sg = s ? 1.0 : -1.0;
-    const double nu[3] = {sg * Ji[d][0] / nn, sg * Ji[d][1] / nn, sg * Ji[d][2] / nn};
-    const double dA = fabs(det) * nn * a.w[pa] * a.w[pb];
-    // J^{-1} nu: reference components of the test-gradient direction
-    const double Jn[3] = {Ji[0][0] * nu[0] + Ji[0][1] * nu[1] + Ji[0][2] * nu[2],
-                          Ji[1][0] * nu[0] + Ji[1][1] * nu[1] + Ji[1][2] * nu[2],
-                          Ji[2][0] * nu[0] + Ji[2][1] * nu[1] + Ji[2][2] * nu[2]};
-    double gradT_n[3];  // (grad u_T,c) . nu
-#pragma unroll
-    for (int c = 0; c < 3; ++c) gradT_n[c] = Jn[0] * gT[c][0] + Jn[1] * gT[c][1] + Jn[2] * gT[c][2];
-    const int plane = ec[d] + s;
-    const int ct1 = ec[t1], ct2 = ec[t2];
-    const double gam = geo.gamma[geo.goff[d] + plane + (int64_t)(a.n[d] + 1) * (ct1 + (int64_t)a.n[t1] * ct2)];
-    double Rv[3], Rg[3], Rq = 0.0;
-    if (has_nb) {
-      // neighbour's full reference gradient at the same physical point
-      double xin[3];
-      xin[d] = (double)(1 - s);
-      xin[t1] = a.xq[pa];
-      xin[t2] = a.xq[pb];
-      double JN[3][3], JiN[3][3];
-      jacobian(nX[f], xin, JN);
-      invert(JN, JiN);
-      const double JnN[3] = {JiN[0][0] * nu[0] + JiN[0][1] * nu[1] + JiN[0][2] * nu[2],
-                             JiN[1][0] * nu[0] + JiN[1][1] * nu[1] + JiN[1][2] * nu[2],
-                             JiN[2][0] * nu[0] + JiN[2][1] * nu[1] + JiN[2][2] * nu[2]};
-      const int fb = f * L;
-      double pN = 0.0;
-#pragma unroll
-      for (int jd = 0; jd < KP; ++jd)
-#pragma unroll
-        for (int ja = 0; ja < KP; ++ja)
-#pragma unroll
-          for (int jb = 0; jb < KP; ++jb) {
-            int pj[3];
-            pj[d] = jd;
-            pj[t1] = ja;
-            pj[t2] = jb;
-            pN = fma(a.ep[1 - s][jd] * a.Ap[pa * KP + ja] * a.Ap[pb * KP + jb],
-                     np_[f][pj[0] + KP * (pj[1] + KP * pj[2])], pN);
-          }
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double gN[3];
-        gN[d] = fDN[c][fp];
-        double ga = 0, gb = 0;
-#pragma unroll
-        for (int j = 0; j < P; ++j) {
-          ga = fma(a.D[pa * P + j], fUN[c][fb + j + P * pb], ga);
-          gb = fma(a.D[pb * P + j], fUN[c][fb + pa + P * j], gb);
-        }
-        gN[t1] = ga;
-        gN[t2] = gb;
-        const double gradN_n = JnN[0] * gN[0] + JnN[1] * gN[1] + JnN[2] * gN[2];
-        const double jump = uT[c] - fUN[c][fp];
-        Rv[c] = dA * (-0.5 * (gradT_n[c] + gradN_n) + gam * jump + 0.5 * (pT + pN) * nu[c]);
-        Rg[c] = dA * 0.5 * a.theta * jump;
-        Rq += dA * 0.5 * jump * nu[c];
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        Rv[c] = dA * (-gradT_n[c] + gam * uT[c] + pT * nu[c]);
-        Rg[c] = dA * a.theta * uT[c];
-        Rq += dA * uT[c] * nu[c];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      fV[c][fp] = Rv[c];
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa) fG[3 * c + aa][fp] = Rg[c] * Jn[aa];
-    }
-    fQ[fp] = Rq;
   }
   __syncthreads();
 
@@ -389,45 +457,79 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1, s = f & 1;
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      int t1, t2;
+      face_dirs(d, t1, t2);
       const int j = ii[d], pa = ii[t1], pb = ii[t2];
       const int fb = f * L;
       const double es = a.e[s][j], des = a.de[s][j];
+      const int fpt = fb + pa + P * pb;
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        double tv = fV[c][fb + pa + P * pb];
+        const double* Rg = fRg + c * NF;
+        double tv = fV[c * NF + fpt];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          tv = fma(a.D[q * P + pa], fG[3 * c + t1][fb + q + P * pb], tv);
-          tv = fma(a.D[q * P + pb], fG[3 * c + t2][fb + pa + P * q], tv);
+          const int f1 = fb + q + P * pb, f2 = fb + pa + P * q;
+          tv = fma(a.D[q * P + pa], Rg[f1] * fJn[t1 * NF + f1], tv);
+          tv = fma(a.D[q * P + pb], Rg[f2] * fJn[t2 * NF + f2], tv);
         }
-        acc[c] = fma(es, tv, fma(des, fG[3 * c + d][fb + pa + P * pb], acc[c]));
+        acc[c] = fma(es, tv, fma(des, Rg[fpt] * fJn[d * NF + fpt], acc[c]));
       }
     }
 #pragma unroll
     for (int c = 0; c < 3; ++c) y[base + c * N + i] = acc[c];
   }
+  // pressure test functions by sum factorization: cell (A_p^T x3) R_p and, per
+  // face, e_p(s) (x) (A_p^T x A_p^T) Q_f
+  double* t1b = tmp;                      // [j0][q1][q2]
+  double* u1 = tmp + KP * P * P;          // [f][ja][pb]
+  for (int i = t; i < KP * P * P; i += NT) {
+    const int j0 = i % KP, q12 = i / KP;
+    double v = 0;
+#pragma unroll
+    for (int q0 = 0; q0 < P; ++q0) v = fma(a.Ap[q0 * KP + j0], sRp[q0 + P * q12], v);
+    t1b[i] = v;
+  }
+  for (int i = t; i < 6 * KP * P; i += NT) {
+    const int f = i / (KP * P), r = i - f * KP * P;
+    const int ja = r % KP, pb = r / KP;
+    double v = 0;
+#pragma unroll
+    for (int pa = 0; pa < P; ++pa) v = fma(a.Ap[pa * KP + ja], fQ[f * L + pa + P * pb], v);
+    u1[i] = v;
+  }
+  __syncthreads();
+  double* t2b = u1 + 6 * KP * P;          // [j0][j1][q2]
+  double* u2 = t2b + KP * KP * P;         // [f][ja][jb]
+  for (int i = t; i < KP * KP * P; i += NT) {
+    const int j0 = i % KP, j1 = (i / KP) % KP, q2 = i / (KP * KP);
+    double v = 0;
+#pragma unroll
+    for (int q1 = 0; q1 < P; ++q1) v = fma(a.Ap[q1 * KP + j1], t1b[j0 + KP * (q1 + P * q2)], v);
+    t2b[i] = v;
+  }
+  for (int i = t; i < 6 * KP * KP; i += NT) {
+    const int f = i / (KP * KP), r = i - f * KP * KP;
+    const int ja = r % KP, jb = r / KP;
+    double v = 0;
+#pragma unroll
+    for (int pb = 0; pb < P; ++pb) v = fma(a.Ap[pb * KP + jb], u1[f * KP * P + ja + KP * pb], v);
+    u2[i] = v;
+  }
+  __syncthreads();
   for (int i = t; i < NQ; i += NT) {
     const int jj[3] = {i % KP, (i / KP) % KP, i / (KP * KP)};
-    double s = 0.0;
-    for (int q = 0; q < N; ++q) {
-      const int q0 = q % P, q1 = (q / P) % P, q2 = q / L;
-      s = fma(a.Ap[q0 * KP + jj[0]] * a.Ap[q1 * KP + jj[1]] * a.Ap[q2 * KP + jj[2]], sRp[q], s);
-    }
+    double v = 0;
+#pragma unroll
+    for (int q2 = 0; q2 < P; ++q2) v = fma(a.Ap[q2 * KP + jj[2]], t2b[jj[0] + KP * (jj[1] + KP * q2)], v);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1, sd = f & 1;
-      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-      const double epv = a.ep[sd][jj[d]];
-      const int fb = f * L;
-      double fs = 0.0;
-      for (int pt = 0; pt < L; ++pt) {
-        const int pa = pt % P, pb = pt / P;
-        fs = fma(a.Ap[pa * KP + jj[t1]] * a.Ap[pb * KP + jj[t2]], fQ[fb + pt], fs);
-      }
-      s = fma(epv, fs, s);
+      const int d = f >> 1, s = f & 1;
+      int t1, t2;
+      face_dirs(d, t1, t2);
+      v = fma(a.ep[s][jj[d]], u2[f * KP * KP + jj[t1] + KP * jj[t2]], v);
     }
-    y[base + 3 * N + i] = s;
+    y[base + 3 * N + i] = v;
   }
 }
 
