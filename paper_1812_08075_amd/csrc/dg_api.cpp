@@ -227,22 +227,11 @@ dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out) 
       fill_scalar_args(*M, M->sd);
       fill_scalar_args(*M, M->sf);
       if (desc->problem == DG_PROBLEM_DIFFREAC) {
-        // line weights w_a w_b (line a + p b), read by the kernels from device memory
-        const int p = M->p;
-        std::vector<double> wl(p * p);
-        std::vector<float> wlf(p * p);
-        for (int b = 0; b < p; ++b)
-          for (int a = 0; a < p; ++a) {
-            wl[a + p * b] = M->tab.wq[a] * M->tab.wq[b];
-            wlf[a + p * b] = (float)M->sf.w[a] * (float)M->sf.w[b];
-          }
-        if (hipMalloc(&M->d_wline, sizeof(double) * p * p) != hipSuccess ||
-            hipMalloc(&M->f_wline, sizeof(float) * p * p) != hipSuccess) {
+        if (hipMalloc(&M->d_pd, sizeof(M->pd)) != hipSuccess || hipMalloc(&M->d_pf, sizeof(M->pf)) != hipSuccess) {
           (void)hipGetLastError();
-          fail(DG_ERR_ALLOC, "device allocation failed (line weights)");
+          fail(DG_ERR_ALLOC, "device allocation failed (parameter blocks)");
         }
-        hip_check(hipMemcpy(M->d_wline, wl.data(), sizeof(double) * p * p, hipMemcpyHostToDevice), "upload");
-        hip_check(hipMemcpy(M->f_wline, wlf.data(), sizeof(float) * p * p, hipMemcpyHostToDevice), "upload");
+        hip_check(dgi::scalar_params_upload(*M), "upload");
       }
       if (desc->problem == DG_PROBLEM_STOKES) dgi::stokes_setup(*M);
       hip_check(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");
@@ -260,8 +249,8 @@ dg_status dg_mesh_destroy(dg_mesh* M) {
     if (!M) return DG_OK;
     if (M->d_vertices) (void)hipFree(M->d_vertices);
     if (M->d_gamma) (void)hipFree(M->d_gamma);
-    if (M->d_wline) (void)hipFree(M->d_wline);
-    if (M->f_wline) (void)hipFree(M->f_wline);
+    if (M->d_pd) (void)hipFree(M->d_pd);
+    if (M->d_pf) (void)hipFree(M->d_pf);
     delete M;
     return DG_OK;
   });

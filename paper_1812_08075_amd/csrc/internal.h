@@ -30,9 +30,12 @@ struct Tables1D {
 void gauss_legendre_golub_welsch(int m, double* x, double* w);
 Tables1D make_tables(int p, int m);
 
-// Kernel arguments of the axis-aligned diffusion-reaction kernels (passed by
-// value, so the tables live in the kernel-argument segment and are read with
-// scalar loads: every lane uses the same entry at the same time).
+// Parameter block of the axis-aligned diffusion-reaction kernels. It lives in
+// device memory (one copy per precision and kernel variant, written once at
+// mesh creation) and the kernels take a pointer to it: every lane uses the
+// same entry at the same time, so the reads are scalar loads issued where the
+// entry is used. Passed by value instead, the whole block would be loaded into
+// scalar registers at kernel entry and spilled.
 template <typename T>
 struct ScalarArgs {
   T D[PMAX * PMAX];    // D[q*P + j] = l_j'(x_q), collocated (m = p)
@@ -62,7 +65,11 @@ struct ScalarArgs {
   T fA[3];               // |F_d| c_cons / 2
   T fG[3];               // |F_d| gamma_d
   T fB[3][2];            // |F_d| c_sym / 2 (2s-1)/h_d
+  T wl[PMAX * PMAX];     // w_a w_b: tangential weight of the line a + p b
 };
+
+// Variants of the parameter block kept per mesh.
+enum : int { SP_APPLY = 0, SP_APPLY_T = 1, SP_ADJOINT = 2, SP_COUNT = 3 };
 
 // Kernel arguments of the Stokes kernels (general trilinear geometry).
 struct StokesArgs {
@@ -93,8 +100,11 @@ struct dg_mesh {
   std::vector<double> vertices;   // host copy (perturbed meshes)
   double* d_vertices = nullptr;   // device copy
   double* d_gamma = nullptr;      // per-face penalties [3][faces of direction d]
-  double* d_wline = nullptr;      // w_a w_b of line a + p b (p^2 entries), FP64
-  float* f_wline = nullptr;       // the same in FP32
+  // parameter blocks of the diffusion-reaction kernels (host copies and device copies)
+  dgi::ScalarArgs<double> pd[dgi::SP_COUNT]{};
+  dgi::ScalarArgs<float> pf[dgi::SP_COUNT]{};
+  dgi::ScalarArgs<double>* d_pd = nullptr;
+  dgi::ScalarArgs<float>* d_pf = nullptr;
   int64_t gamma_off[3] = {0, 0, 0};
 };
 
@@ -108,6 +118,9 @@ void derive_face_constants(ScalarArgs<T>& a);
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa,
                           void* ATg, void* dkappa, hipStream_t s);
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s);
+// Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,
+// line weights) and uploads them to M.d_pd / M.d_pf (allocated by the caller).
+hipError_t scalar_params_upload(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
 
 // Vector kernels of the solvers (deterministic fixed-order reductions).

@@ -15,8 +15,8 @@
 //  * On axis-aligned cells J = diag(h), so the pointwise stage of direction d
 //    only needs d_d u: kappa w |J| / h_d^2 * d_d u. Contraction, quadrature
 //    and transposed contraction of one direction therefore run on one 1D
-//    line of p values in one thread, with D from the kernel-argument segment
-//    (wave-uniform scalar operands). A cell is handled by p^2 threads that
+//    line of p values in one thread, with D from a device-resident parameter
+//    block (wave-uniform scalar operands). A cell is handled by p^2 threads that
 //    own, in turn, its p^2 lines along x, along y and along z.
 //  * Faces normal to d (Section 2.2, m_d = 1, normal direction contracted
 //    first) sit at the two ends of every d-line: the own trace u and its
@@ -241,7 +241,8 @@ __device__ __forceinline__ void neighbor_lines(const T* __restrict__ s, const T*
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
-                   const T* __restrict__ wline, const ScalarArgs<T> a) {
+                   const ScalarArgs<T>* __restrict__ ap) {
+  const ScalarArgs<T>& a = *ap;
   constexpr int EB = CellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
@@ -262,21 +263,13 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const int ex = ex0 + le;
   const uint32_t e = row + ex;
   const uint32_t nxy = (uint32_t)nx * ny;
-  // the y- and z-neighbour lines come from global memory (L2) and do not depend
-  // on the LDS stage: issue them together with the cell loads
   T nb1[2][P], nk1[2][P], nb2[2][P], nk2[2][P];
   bool has1[2], has2[2];
-  if (active) {
-    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb1, has1);
-    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk1, has1);
-    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb2, has2);
-    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk2, has2);
-  }
   load_cells<P, T>(sx, x, gbase, nvalid, NT);
   if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
   __syncthreads();
 
-  const T wt = wline[li];  // tangential weight w_ta w_tb of this thread's lines
+  const T wt = a.wl[li];  // tangential weight w_ta w_tb of this thread's lines
   const T* sxe = sx + le * Ly::NP;
   const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
   T out0[P], out1[P], out2[P];
@@ -293,6 +286,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     // lines along y: (i0, i2) = (ta, tb)
     lds_line<P, T, 1>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
+    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb1, has1);
+    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk1, has1);
     line_apply<P, T, KAPPA, 1>(v, kv, nb1, nk1, has1, a, false, out1);
 #pragma unroll
     for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
@@ -308,6 +303,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     T v[P], kv[P];
     lds_line<P, T, 2>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
+    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb2, has2);
+    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk2, has2);
     line_apply<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
   }
   __syncthreads();
@@ -447,8 +444,8 @@ __device__ __forceinline__ void adjoint_direction(const T* sge, const T* sue, co
 template <int P, typename T, bool KAPPA>
 __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
     k_scalar_adjoint(const T* __restrict__ g, const T* __restrict__ u, const T* __restrict__ kappa,
-                     T* __restrict__ ATg, T* __restrict__ dkappa, const T* __restrict__ wline,
-                     const ScalarArgs<T> a) {
+                     T* __restrict__ ATg, T* __restrict__ dkappa, const ScalarArgs<T>* __restrict__ ap) {
+  const ScalarArgs<T>& a = *ap;
   constexpr int EB = AdjCellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
@@ -471,7 +468,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
-  const T wt = wline[li];
+  const T wt = a.wl[li];
   T og2[P], ok2[P];
   if (active) {
     const int ex = ex0 + le;
@@ -512,7 +509,9 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
 
 // b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
 template <int P, typename T>
-__global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const ScalarArgs<T> a, int64_t n) {
+__global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const ScalarArgs<T>* __restrict__ ap,
+                              int64_t n) {
+  const ScalarArgs<T>& a = *ap;
   constexpr int N = P * P * P;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -531,40 +530,55 @@ int64_t sweep_grid(ScalarArgs<T>& a, int eb) {
 }
 
 template <typename T>
-const T* line_weights(const dg_mesh& M);
+const ScalarArgs<T>* host_params(const dg_mesh& M);
 template <>
-const double* line_weights<double>(const dg_mesh& M) { return M.d_wline; }
+const ScalarArgs<double>* host_params<double>(const dg_mesh& M) { return M.pd; }
 template <>
-const float* line_weights<float>(const dg_mesh& M) { return M.f_wline; }
+const ScalarArgs<float>* host_params<float>(const dg_mesh& M) { return M.pf; }
+template <typename T>
+const ScalarArgs<T>* device_params(const dg_mesh& M);
+template <>
+const ScalarArgs<double>* device_params<double>(const dg_mesh& M) { return M.d_pd; }
+template <>
+const ScalarArgs<float>* device_params<float>(const dg_mesh& M) { return M.d_pf; }
+
+// Grid size of a parameter block whose sweep fields are already set.
+template <typename T>
+int64_t grid_of(const ScalarArgs<T>& a) {
+  return (int64_t)a.nchunk * a.n[1] * a.n[2];
+}
 
 template <int P, typename T>
-hipError_t launch_apply(const dg_mesh& M, ScalarArgs<T> a, const T* x, T* y, const T* kappa, hipStream_t s) {
+hipError_t launch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, hipStream_t s) {
   constexpr int EB = CellsPerBlock<P>::value;
-  const int64_t G = sweep_grid(a, EB);
+  const int64_t G = grid_of(host_params<T>(M)[variant]);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
-  const T* wl = line_weights<T>(M);
+  const ScalarArgs<T>* ap = device_params<T>(M) + variant;
   if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, wl, a);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, ap);
   else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, wl, a);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, ap);
   return hipGetLastError();
 }
 
 template <int P, typename T>
-hipError_t launch_adjoint(const dg_mesh& M, ScalarArgs<T> a, const T* g, const T* u, const T* kappa, T* ATg, T* dk,
-                          hipStream_t s) {
+hipError_t launch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* kappa, T* ATg, T* dk, hipStream_t s) {
   constexpr int EB = AdjCellsPerBlock<P>::value;
-  const int64_t G = sweep_grid(a, EB);
+  const int64_t G = grid_of(host_params<T>(M)[SP_ADJOINT]);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
-  const T* wl = line_weights<T>(M);
+  const ScalarArgs<T>* ap = device_params<T>(M) + SP_ADJOINT;
   if (kappa)
     hipLaunchKernelGGL((k_scalar_adjoint<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, g, u, kappa, ATg,
-                       dk, wl, a);
+                       dk, ap);
   else
     hipLaunchKernelGGL((k_scalar_adjoint<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, g, u, kappa,
-                       ATg, dk, wl, a);
+                       ATg, dk, ap);
   return hipGetLastError();
 }
+
+// Cells per block of the apply and adjoint kernels for p nodes per direction.
+int apply_cells_per_block(int p) { return 256 / (p * p) > 0 ? 256 / (p * p) : 1; }
+int adjoint_cells_per_block(int p) { return 128 / (p * p) > 0 ? 128 / (p * p) : 1; }
 
 #define DG_DISPATCH_P(P_, CALL)           \
   switch (P_) {                           \
@@ -579,28 +593,28 @@ hipError_t launch_adjoint(const dg_mesh& M, ScalarArgs<T> a, const T* g, const T
   }
 
 template <typename T>
-hipError_t dispatch_apply(const dg_mesh& M, const ScalarArgs<T>& a, const T* x, T* y, const T* kappa,
-                          hipStream_t s) {
-#define DG_CALL(PP) launch_apply<PP, T>(M, a, x, y, kappa, s)
+hipError_t dispatch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, hipStream_t s) {
+#define DG_CALL(PP) launch_apply<PP, T>(M, variant, x, y, kappa, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
 
 template <typename T>
-hipError_t dispatch_adjoint(const dg_mesh& M, const ScalarArgs<T>& a, const T* g, const T* u, const T* kappa,
-                            T* ATg, T* dk, hipStream_t s) {
-#define DG_CALL(PP) launch_adjoint<PP, T>(M, a, g, u, kappa, ATg, dk, s)
+hipError_t dispatch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* kappa, T* ATg, T* dk,
+                            hipStream_t s) {
+#define DG_CALL(PP) launch_adjoint<PP, T>(M, g, u, kappa, ATg, dk, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
 
 template <typename T>
-hipError_t dispatch_load(const dg_mesh& M, const ScalarArgs<T>& a, const T* f, T* b, hipStream_t s) {
+hipError_t dispatch_load(const dg_mesh& M, const T* f, T* b, hipStream_t s) {
   const int64_t n = M.ndofs;
   const unsigned G = (unsigned)((n + 255) / 256);
+  const ScalarArgs<T>* ap = device_params<T>(M) + SP_APPLY;
   switch (M.p) {
 #define DG_LOAD_CASE(PP) \
-  case PP: hipLaunchKernelGGL((k_scalar_load<PP, T>), dim3(G), dim3(256), 0, s, f, b, a, n); break;
+  case PP: hipLaunchKernelGGL((k_scalar_load<PP, T>), dim3(G), dim3(256), 0, s, f, b, ap, n); break;
     DG_LOAD_CASE(2) DG_LOAD_CASE(3) DG_LOAD_CASE(4) DG_LOAD_CASE(5) DG_LOAD_CASE(6) DG_LOAD_CASE(7)
     DG_LOAD_CASE(8)
 #undef DG_LOAD_CASE
@@ -609,38 +623,53 @@ hipError_t dispatch_load(const dg_mesh& M, const ScalarArgs<T>& a, const T* f, T
   return hipGetLastError();
 }
 
+template <typename T>
+void fill_params(const ScalarArgs<T>& base, const Tables1D& tab, int p, ScalarArgs<T>* out) {
+  for (int v = 0; v < SP_COUNT; ++v) {
+    ScalarArgs<T> a = base;
+    if (v == SP_APPLY_T) {
+      std::swap(a.c_cons, a.c_sym);
+      derive_face_constants(a);
+    }
+    sweep_grid(a, v == SP_ADJOINT ? adjoint_cells_per_block(p) : apply_cells_per_block(p));
+    for (int tb = 0; tb < p; ++tb)
+      for (int ta = 0; ta < p; ++ta) {
+        // rounded to T first, then multiplied in T, as the kernels' other weights
+        a.wl[ta + p * tb] = (T)tab.wq[ta] * (T)tab.wq[tb];
+      }
+    out[v] = a;
+  }
+}
+
 }  // namespace
 
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa, bool transpose,
                         hipStream_t s) {
-  if (prec == DG_F64) {
-    ScalarArgs<double> a = M.sd;
-    if (transpose) {
-      std::swap(a.c_cons, a.c_sym);
-      derive_face_constants(a);
-    }
-    return dispatch_apply<double>(M, a, (const double*)x, (double*)y, (const double*)kappa, s);
-  }
-  ScalarArgs<float> a = M.sf;
-  if (transpose) {
-    std::swap(a.c_cons, a.c_sym);
-    derive_face_constants(a);
-  }
-  return dispatch_apply<float>(M, a, (const float*)x, (float*)y, (const float*)kappa, s);
+  const int v = transpose ? SP_APPLY_T : SP_APPLY;
+  if (prec == DG_F64) return dispatch_apply<double>(M, v, (const double*)x, (double*)y, (const double*)kappa, s);
+  return dispatch_apply<float>(M, v, (const float*)x, (float*)y, (const float*)kappa, s);
 }
 
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa, void* ATg,
                           void* dkappa, hipStream_t s) {
   if (prec == DG_F64)
-    return dispatch_adjoint<double>(M, M.sd, (const double*)g, (const double*)u, (const double*)kappa,
-                                    (double*)ATg, (double*)dkappa, s);
-  return dispatch_adjoint<float>(M, M.sf, (const float*)g, (const float*)u, (const float*)kappa, (float*)ATg,
+    return dispatch_adjoint<double>(M, (const double*)g, (const double*)u, (const double*)kappa, (double*)ATg,
+                                    (double*)dkappa, s);
+  return dispatch_adjoint<float>(M, (const float*)g, (const float*)u, (const float*)kappa, (float*)ATg,
                                  (float*)dkappa, s);
 }
 
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s) {
-  if (prec == DG_F64) return dispatch_load<double>(M, M.sd, (const double*)fq, (double*)b, s);
-  return dispatch_load<float>(M, M.sf, (const float*)fq, (float*)b, s);
+  if (prec == DG_F64) return dispatch_load<double>(M, (const double*)fq, (double*)b, s);
+  return dispatch_load<float>(M, (const float*)fq, (float*)b, s);
+}
+
+hipError_t scalar_params_upload(dg_mesh& M) {
+  fill_params(M.sd, M.tab, M.p, M.pd);
+  fill_params(M.sf, M.tab, M.p, M.pf);
+  hipError_t e = hipMemcpy(M.d_pd, M.pd, sizeof(M.pd), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(M.d_pf, M.pf, sizeof(M.pf), hipMemcpyHostToDevice);
 }
 
 }  // namespace dgi
