@@ -130,6 +130,42 @@ void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
     a.fG[d] = (T)(detJ / h[d] * coef / h[d]);
   }
   for (int i = 0; i < p; ++i) a.cw[i] = (T)(M.desc.c * detJ * t.wq[i]);
+  // even-odd split (computed in FP64 from the 1D tables, then rounded)
+  const int H = p / 2;
+  for (int d = 0; d < 3; ++d) {
+    dgi::EvenOdd<T>& o = a.eo[d];
+    const double vsd = detJ / (h[d] * h[d]);
+    auto Dv = [&](int q, int j) { return vsd * t.wq[q] * t.D[q][j]; };
+    for (int q = 0; q < H; ++q) {
+      for (int j = 0; j < H; ++j) {
+        o.DvP[q * H + j] = (T)(0.5 * (Dv(q, j) + Dv(q, p - 1 - j)));
+        o.DvM[q * H + j] = (T)(0.5 * (Dv(q, j) - Dv(q, p - 1 - j)));
+      }
+      if (p & 1) {
+        o.DvC[q] = (T)Dv(q, H);
+        o.DvR[q] = (T)Dv(H, q);
+      }
+    }
+    o.fG = a.fG[d];
+  }
+  for (int i = 0; i < H; ++i) {
+    for (int q = 0; q < H; ++q) {
+      a.G2p[i * H + q] = (T)(t.D[q][i] + t.D[q][p - 1 - i]);
+      a.G2m[i * H + q] = (T)(t.D[q][i] - t.D[q][p - 1 - i]);
+    }
+    if (p & 1) {
+      a.Gh[i] = (T)t.D[H][i];
+      a.G2c[i] = (T)(2.0 * t.D[i][H]);
+    }
+    a.Ep[i] = (T)(0.5 * (t.e[0][i] + t.e[0][p - 1 - i]));
+    a.Em[i] = (T)(0.5 * (t.e[0][i] - t.e[0][p - 1 - i]));
+    a.DEp[i] = (T)(0.5 * (t.de[0][i] + t.de[0][p - 1 - i]));
+    a.DEm[i] = (T)(0.5 * (t.de[0][i] - t.de[0][p - 1 - i]));
+    a.cwh[i] = (T)(0.5 * M.desc.c * detJ * t.wq[i]);
+  }
+  a.Eh = (T)((p & 1) ? t.e[0][H] : 0.0);
+  a.DEh = (T)((p & 1) ? t.de[0][H] : 0.0);
+  a.cwm = (T)((p & 1) ? M.desc.c * detJ * t.wq[H] : 0.0);
   dgi::derive_face_constants(a);
 }
 
@@ -162,6 +198,8 @@ void dgi::derive_face_constants(ScalarArgs<T>& a) {
     const double fs = (double)a.fs[d], hi = (double)a.hinv[d];
     a.fA[d] = (T)(fs * 0.5 * (double)a.c_cons);
     for (int s = 0; s < 2; ++s) a.fB[d][s] = (T)(fs * 0.5 * (double)a.c_sym * (s ? 1.0 : -1.0) * hi);
+    a.eo[d].fAh = (T)(-fs * 0.5 * (double)a.c_cons * hi);
+    a.eo[d].fB0 = a.fB[d][0];
   }
 }
 template void dgi::derive_face_constants<double>(ScalarArgs<double>&);

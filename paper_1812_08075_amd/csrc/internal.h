@@ -12,6 +12,7 @@
 namespace dgi {
 
 constexpr int PMAX = 8;  // largest number of 1D nodes or points (degree 7)
+constexpr int HMAX = PMAX / 2;
 
 // 1D Gauss-Legendre rule on [0,1] and nodal Lagrange tables (Section 2.2: the
 // basis matrices A^(i), D^(i) and the face rows used with m_d = 1).
@@ -29,6 +30,18 @@ struct Tables1D {
 
 void gauss_legendre_golub_welsch(int m, double* x, double* w);
 Tables1D make_tables(int p, int m);
+
+// Even-odd volume tables of one direction (see ScalarArgs::eo).
+template <typename T>
+struct EvenOdd {
+  T DvP[HMAX * HMAX];  // [q H + j] (Dv_qj + Dv_q,p-1-j) / 2
+  T DvM[HMAX * HMAX];  // [q H + j] (Dv_qj - Dv_q,p-1-j) / 2
+  T DvC[HMAX];         // Dv_qH (odd p)
+  T DvR[HMAX];         // Dv_Hj (odd p): middle point, from the odd part
+  T fAh;               // -|F| c_cons / (2 h): consistency term on reference-coordinate derivatives
+  T fG;                // |F| gamma
+  T fB0;               // |F| c_sym / 2 (-1/h): symmetry term of side 0
+};
 
 // Parameter block of the axis-aligned diffusion-reaction kernels. It lives in
 // device memory (one copy per precision and kernel variant, written once at
@@ -66,6 +79,22 @@ struct ScalarArgs {
   T fG[3];               // |F_d| gamma_d
   T fB[3][2];            // |F_d| c_sym / 2 (2s-1)/h_d
   T wl[PMAX * PMAX];     // w_a w_b: tangential weight of the line a + p b
+  // Even-odd split of the tables (H = p / 2, middle index H when p is odd).
+  // The nodes are symmetric about the cell centre, so the derivative matrix
+  // is centro-antisymmetric and the face rows of side 1 are the mirror images
+  // of those of side 0 (the derivative row with a sign). A line v is carried
+  // as ve_j = v_j + v_{p-1-j}, vo_j = v_j - v_{p-1-j} (j < H) and the middle
+  // value; an output as half sums oe_i and half differences oo_i
+  // (out_i = oe_i + oo_i, out_{p-1-i} = oe_i - oo_i) and the middle value.
+  // Only the volume rows depend on the direction.
+  EvenOdd<T> eo[3];
+  T G2p[HMAX * HMAX];  // [i H + q] D_qi + D_q,p-1-i: transposed contraction of the odd part of r
+  T G2m[HMAX * HMAX];  // [i H + q] D_qi - D_q,p-1-i: of the even part
+  T Gh[HMAX];          // D_Hi (odd p)
+  T G2c[HMAX];         // 2 D_qH (odd p): middle output
+  T Ep[HMAX], Em[HMAX], Eh;     // (e0_j +- e0_{p-1-j}) / 2 and e0_H
+  T DEp[HMAX], DEm[HMAX], DEh;  // the same of de0
+  T cwh[HMAX], cwm;             // c |J| w_i / 2 and c |J| w_H (mass term)
 };
 
 // Variants of the parameter block kept per mesh.

@@ -125,70 +125,151 @@ __device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restric
 // Volume and face work of one 1D line of one cell in direction DIR, without
 // the line's tangential quadrature weight w_a w_b, which the caller applies once.
 //  v, kv: the line's values and kappa at its nodes; nb[s], nk[s]: the
-//  neighbour's matching line across side s (unused when !has_nb[s]);
+//  neighbour's matching line across side s (zero where there is none);
 //  mass: add the c |J| w u term (once per cell, on the x lines).
+// The line is split into its even and odd parts about the cell centre (the
+// even-odd tables of ScalarArgs): the contractions with D and D^T and the
+// traces at both ends then each cost about half the multiplications.
 template <int P, typename T, bool KAPPA, int DIR>
 __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
                                            const bool* has_nb, const ScalarArgs<T>& a, bool mass, T* out) {
-  // cell: r_q = kappa_q (|J|/h^2) w_q (D v)_q (contraction to the points and
-  // quadrature scaling in one table), out = D^T r
-  T r[P];
+  constexpr int H = P / 2;
+  constexpr bool ODD = (P & 1) != 0;
+  const EvenOdd<T>& dv = a.eo[DIR];
+  T ve[H], vo[H];
 #pragma unroll
-  for (int q = 0; q < P; ++q) {
-    T du = T(0);
-#pragma unroll
-    for (int j = 0; j < P; ++j) du = fma(a.Dv[DIR][q * P + j], v[j], du);
-    r[q] = KAPPA ? kv[q] * du : du;
+  for (int j = 0; j < H; ++j) {
+    ve[j] = v[j] + v[P - 1 - j];
+    vo[j] = v[j] - v[P - 1 - j];
   }
+  const T vm = ODD ? v[H] : T(0);
+  // cell: d = (|J|/h^2) w D v at the points, as d_q = se_q + so_q,
+  // d_{p-1-q} = so_q - se_q (q < H) and the middle value dm
+  T se[H], so[H];
 #pragma unroll
-  for (int i = 0; i < P; ++i) {
-    T s = mass ? a.cw[i] * v[i] : T(0);
+  for (int q = 0; q < H; ++q) {
+    T s0 = ODD ? dv.DvC[q] * vm : T(0), s1 = T(0);
 #pragma unroll
-    for (int q = 0; q < P; ++q) s = fma(a.D[q * P + i], r[q], s);
-    out[i] = s;
+    for (int j = 0; j < H; ++j) {
+      s0 = fma(dv.DvP[q * H + j], ve[j], s0);
+      s1 = fma(dv.DvM[q * H + j], vo[j], s1);
+    }
+    se[q] = s0;
+    so[q] = s1;
   }
-  // faces at both ends of the line
+  T dm = T(0);
+  if (ODD) {
+#pragma unroll
+    for (int j = 0; j < H; ++j) dm = fma(dv.DvR[j], vo[j], dm);
+  }
+  // r = kappa d as half sums re and half differences ro over mirrored points
+  T re[H], ro[H], rm;
+  T ks[H], kd[H];  // kappa_j + kappa_{p-1-j}, kappa_j - kappa_{p-1-j}
+  if (KAPPA) {
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      ks[q] = kv[q] + kv[P - 1 - q];
+      kd[q] = kv[q] - kv[P - 1 - q];
+      const T ke = T(0.5) * ks[q], ko = T(0.5) * kd[q];
+      re[q] = fma(ko, se[q], ke * so[q]);
+      ro[q] = fma(ke, se[q], ko * so[q]);
+    }
+    rm = ODD ? kv[H] * dm : T(0);
+  } else {
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      re[q] = so[q];
+      ro[q] = se[q];
+    }
+    rm = dm;
+  }
+  // out = D^T r (+ mass) accumulated as half sums oe and half differences oo
+  T oe[H], oo[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T t0 = mass ? a.cwh[i] * ve[i] : T(0);
+    T t1 = mass ? a.cwh[i] * vo[i] : T(0);
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+      t0 = fma(a.G2p[i * H + q], ro[q], t0);
+      t1 = fma(a.G2m[i * H + q], re[q], t1);
+    }
+    if (ODD) t1 = fma(a.Gh[i], rm, t1);
+    oe[i] = t0;
+    oo[i] = t1;
+  }
+  T om = T(0);
+  if (ODD) {
+    om = mass ? a.cwm * vm : T(0);
+#pragma unroll
+    for (int q = 0; q < H; ++q) om = fma(a.G2c[q], ro[q], om);
+  }
+  // own traces and reference-coordinate derivatives at both ends: side 1 uses
+  // the mirror image of the side-0 rows (the derivative row with a sign)
+  T ae = ODD ? a.Eh * vm : T(0), bo = T(0), pe = ODD ? a.DEh * vm : T(0), qo = T(0);
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    ae = fma(a.Ep[j], ve[j], ae);
+    bo = fma(a.Em[j], vo[j], bo);
+    pe = fma(a.DEp[j], ve[j], pe);
+    qo = fma(a.DEm[j], vo[j], qo);
+  }
+  const T uT[2] = {ae + bo, ae - bo};
+  // outward normal derivative = -(1/h) dT (the -1/h sits in fAh)
+  const T dT[2] = {pe + qo, pe - qo};
   const bool face_kappa = KAPPA && !a.kappa_face_one;
+  T kT[2] = {T(1), T(1)};
+  if (face_kappa) {
+    T ka = ODD ? a.Eh * kv[H] : T(0), kb = T(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      ka = fma(a.Ep[j], ks[j], ka);
+      kb = fma(a.Em[j], kd[j], kb);
+    }
+    kT[0] = ka + kb;
+    kT[1] = ka - kb;
+  }
+  // face fluxes: Rv multiplies the trace row of side s, Sd (times fB0) its derivative row
+  T Rv[2], Sd[2];
 #pragma unroll
   for (int s = 0; s < 2; ++s) {
     const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
-    if (!has_nb[s] && !dirichlet) continue;
-    T uT = T(0), dnuT = T(0);  // own trace and outward normal derivative
+    // the neighbour across side s meets it with its own side 1-s: trace row
+    // e0 mirrored for s = 0, e0 for s = 1; derivative row likewise (no branch:
+    // the neighbour line is zero where there is none)
+    T uN = T(0), dN = T(0), kN = T(1);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      uT = fma(a.e[s][j], v[j], uT);
-      dnuT = fma(a.dno[DIR][s][j], v[j], dnuT);
+      const int r = s == 0 ? P - 1 - j : j;
+      uN = fma(a.e[0][r], nb[s][j], uN);
+      dN = fma(a.de[0][r], nb[s][j], dN);
     }
-    T kT = T(1);
     if (face_kappa) {
-      kT = T(0);
+      kN = T(0);
 #pragma unroll
-      for (int j = 0; j < P; ++j) kT = fma(a.e[s][j], kv[j], kT);
+      for (int j = 0; j < P; ++j) kN = fma(a.e[0][s == 0 ? P - 1 - j : j], nk[s][j], kN);
     }
-    T Rv, Rdv;
-    if (has_nb[s]) {
-      T uN = T(0), dnuN = T(0);  // neighbour's trace and its own outward normal derivative
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        uN = fma(a.e[1 - s][j], nb[s][j], uN);
-        dnuN = fma(a.dni[DIR][s][j], nb[s][j], dnuN);
-      }
-      T kN = T(1);
-      if (face_kappa) {
-        kN = T(0);
-#pragma unroll
-        for (int j = 0; j < P; ++j) kN = fma(a.e[1 - s][j], nk[s][j], kN);
-      }
-      const T jump = uT - uN;
-      Rv = fma(a.fA[DIR], kT * dnuT - kN * dnuN, a.fG[DIR] * jump);
-      Rdv = a.fB[DIR][s] * (kT * jump);
-    } else {
-      Rv = fma(T(2) * a.fA[DIR], kT * dnuT, a.fG[DIR] * uT);
-      Rdv = T(2) * a.fB[DIR][s] * (kT * uT);
-    }
-#pragma unroll
-    for (int i = 0; i < P; ++i) out[i] = fma(Rv, a.e[s][i], fma(Rdv, a.de[s][i], out[i]));
+    // interior: averages and jumps; Dirichlet: the one-sided terms count twice
+    const T sel = has_nb[s] ? T(1) : (dirichlet ? T(2) : T(0));
+    const T g = (has_nb[s] || dirichlet) ? dv.fG : T(0);
+    const T jump = uT[s] - uN;
+    Rv[s] = fma(sel * dv.fAh, kT[s] * dT[s] - kN * dN, g * jump);
+    Sd[s] = sel * (kT[s] * jump);
   }
+  const T cE = Rv[0] + Rv[1], cO = Rv[0] - Rv[1];
+  const T dE = dv.fB0 * (Sd[0] + Sd[1]), dO = dv.fB0 * (Sd[0] - Sd[1]);
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    oe[i] = fma(cE, a.Ep[i], fma(dE, a.DEp[i], oe[i]));
+    oo[i] = fma(cO, a.Em[i], fma(dO, a.DEm[i], oo[i]));
+  }
+  if (ODD) om = fma(cE, a.Eh, fma(dE, a.DEh, om));
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    out[i] = oe[i] + oo[i];
+    out[P - 1 - i] = oe[i] - oo[i];
+  }
+  if (ODD) out[H] = om;
 }
 
 // Reads the line of direction DIR at (ta, tb) of LDS cell block `sc`.
