@@ -68,7 +68,7 @@ enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2 };
 
 /* Mesh and operator description (all fields are read by dg_mesh_create). */
 typedef struct {
-  int32_t nx, ny, nz;       /* cells per direction, >= 1 */
+  int32_t nx, ny, nz;       /* cells per direction, 1 .. 65535 */
   int32_t k;                /* polynomial degree (velocity degree for Stokes) */
   int32_t m;                /* Gauss-Legendre points per direction; 0 -> k + 1 */
   int32_t problem;          /* DG_PROBLEM_* */

@@ -50,6 +50,7 @@ int quad_points(const dg_mesh_desc& d) { return d.m == 0 ? d.k + 1 : d.m; }
 void validate(const dg_mesh_desc* d) {
   if (!d) fail(DG_ERR_ARG, "desc is NULL");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) fail(DG_ERR_ARG, "nx, ny, nz must be >= 1");
+  if (d->nx > 65535 || d->ny > 65535 || d->nz > 65535) fail(DG_ERR_ARG, "nx, ny, nz must be <= 65535");
   if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES) fail(DG_ERR_ARG, "unknown problem");
   if (d->k < 1) fail(DG_ERR_ARG, "k must be >= 1");
   if (d->m < 0) fail(DG_ERR_ARG, "m must be >= 0");
@@ -111,6 +112,13 @@ void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
     a.n[d] = n[d];
   }
   a.cmass = (T)(M.desc.c * detJ);
+  a.p = p;
+  for (int d = 0; d < 3; ++d) {
+    a.hd[d] = h[d];
+    a.gamd[d] = coef / h[d];
+  }
+  a.detJd = detJ;
+  a.cd = M.desc.c;
   a.c_cons = (T)(-1.0);
   a.c_sym = (T)M.desc.theta;
   a.nelem = (int32_t)M.nelem;
@@ -201,6 +209,61 @@ void dgi::derive_face_constants(ScalarArgs<T>& a) {
     a.eo[d].fAh = (T)(-fs * 0.5 * (double)a.c_cons * hi);
     a.eo[d].fB0 = a.fB[d][0];
   }
+  // 1D line operators (kappa = 1), in long double from the FP64 geometry
+  using ld = long double;
+  const int p = a.p;
+  if (p == 4) {
+    const ld cc = (ld)(double)a.c_cons, cs = (ld)(double)a.c_sym;
+    for (int d = 0; d < 3; ++d) {
+      const ld h = a.hd[d], detJ = a.detJd;
+      const ld vs = detJ / (h * h), fs = detJ / h;
+      const ld fA = fs * cc / 2, fG = fs * (ld)a.gamd[d];
+      const ld fB[2] = {-fs * cs / 2 / h, fs * cs / 2 / h};
+      ld e[2][4], de[2][4], nrm[2][4];
+      for (int s = 0; s < 2; ++s)
+        for (int j = 0; j < 4; ++j) {
+          e[s][j] = (ld)(double)a.e[s][j];
+          de[s][j] = (ld)(double)a.de[s][j];
+          nrm[s][j] = (s ? 1 : -1) * de[s][j] / h;  // outward normal derivative row of side s
+        }
+      ld Kvol[4][4];
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          ld acc = 0;
+          for (int q = 0; q < 4; ++q)
+            acc += (ld)(double)a.D[q * 4 + i] * vs * (ld)(double)a.w[q] * (ld)(double)a.D[q * 4 + j];
+          if (d == 0 && i == j) acc += (ld)a.cd * detJ * (ld)(double)a.w[i];
+          Kvol[i][j] = acc;
+        }
+      // own-cell face terms of side s for side type t (0 interior, 1 Dirichlet, 2 none)
+      auto face = [&](int s, int t, int i, int j) -> ld {
+        if (t == 2) return 0;
+        const ld two = t == 1 ? 2 : 1;
+        return two * fA * e[s][i] * nrm[s][j] + fG * e[s][i] * e[s][j] + two * fB[s] * de[s][i] * e[s][j];
+      };
+      for (int t0 = 0; t0 < 3; ++t0)
+        for (int t1 = 0; t1 < 3; ++t1)
+          for (int i = 0; i < 4; ++i)
+            for (int j = 0; j < 4; ++j)
+              a.Km[d][3 * t0 + t1][4 * i + j] = (T)(Kvol[i][j] + face(0, t0, i, j) + face(1, t1, i, j));
+      for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) {
+          // neighbour across side 0 meets it with its side 1, across side 1 with its side 0
+          a.Lm[d][4 * i + j] = (T)(-fA * e[0][i] * nrm[1][j] - fG * e[0][i] * e[1][j] - fB[0] * de[0][i] * e[1][j]);
+          a.Rm[d][4 * i + j] = (T)(-fA * e[1][i] * nrm[0][j] - fG * e[1][i] * e[0][j] - fB[1] * de[1][i] * e[0][j]);
+        }
+    }
+    for (int lane = 0; lane < 64; ++lane) {
+      const int ai = 4 * (lane & 3) + (lane >> 4);
+      const int t1 = lane & 3, t2 = (lane >> 2) & 3;
+      for (int d = 0; d < 3; ++d) {
+        a.lrec[lane][3 * d] = (double)a.Km[d][0][ai];
+        a.lrec[lane][3 * d + 1] = (double)a.Lm[d][ai];
+        a.lrec[lane][3 * d + 2] = (double)a.Rm[d][ai];
+      }
+      a.lrec[lane][9] = (double)a.w[t1] * (double)a.w[t2];
+    }
+  }
 }
 template void dgi::derive_face_constants<double>(ScalarArgs<double>&);
 template void dgi::derive_face_constants<float>(ScalarArgs<float>&);
@@ -270,6 +333,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out) 
           fail(DG_ERR_ALLOC, "device allocation failed (parameter blocks)");
         }
         hip_check(dgi::scalar_params_upload(*M), "upload");
+        hip_check(dgi::mfma_setup(*M), "upload");
       }
       if (desc->problem == DG_PROBLEM_STOKES) dgi::stokes_setup(*M);
       hip_check(hipStreamSynchronize(as_stream(stream)), "hipStreamSynchronize");
@@ -289,6 +353,8 @@ dg_status dg_mesh_destroy(dg_mesh* M) {
     if (M->d_gamma) (void)hipFree(M->d_gamma);
     if (M->d_pd) (void)hipFree(M->d_pd);
     if (M->d_pf) (void)hipFree(M->d_pf);
+    if (M->d_blocks) (void)hipFree(M->d_blocks);
+    if (M->d_waves) (void)hipFree(M->d_waves);
     delete M;
     return DG_OK;
   });

@@ -50,7 +50,7 @@ struct EvenOdd {
 // entry is used. Passed by value instead, the whole block would be loaded into
 // scalar registers at kernel entry and spilled.
 template <typename T>
-struct ScalarArgs {
+struct alignas(16) ScalarArgs {
   T D[PMAX * PMAX];    // D[q*P + j] = l_j'(x_q), collocated (m = p)
   T e[2][PMAX];        // face trace rows
   T de[2][PMAX];       // face derivative rows (reference coordinates)
@@ -69,6 +69,9 @@ struct ScalarArgs {
   // blocks are swept as (slab of sz z-planes, y, z within the slab, chunk)
   int32_t nchunk;      // chunks per x-row
   int32_t sz;          // z-planes per slab
+  // per hardware block: (first cell's x index | y << 16, z) of its chunk, in the
+  // sweep order with the XCD renumbering applied (table written at mesh creation)
+  const uint32_t* blocks;
   // Per-direction tables with the constant factors folded in; a line's
   // tangential weight w_a w_b multiplies its whole result once at the end.
   T Dv[3][PMAX * PMAX];  // (|J|/h_d^2) w_q l_j'(x_q): contraction to the points plus quadrature scaling
@@ -79,6 +82,22 @@ struct ScalarArgs {
   T fG[3];               // |F_d| gamma_d
   T fB[3][2];            // |F_d| c_sym / 2 (2s-1)/h_d
   T wl[PMAX * PMAX];     // w_a w_b: tangential weight of the line a + p b
+  // 1D line operators for kappa = 1 (the matrix-core apply, p = 4): along a
+  // line of direction d, out = K u + L u_left + R u_right before the line's
+  // tangential weight, where K holds the volume term (and the mass term for
+  // d = 0) and the own-cell face terms, L and R the neighbour face terms.
+  // K has one variant per pair of side types (interior, Dirichlet, none):
+  // index 3 t0 + t1. Row-major 4 x 4.
+  T Km[3][9][16];
+  T Lm[3][16];
+  T Rm[3][16];
+  // per lane of the matrix-core apply: the A operands of the interior cell
+  // (Kx, Lx, Rx, Ky, Ly, Ry, Kz, Lz, Rz, entry (lane % 4, lane / 16)) and the
+  // tangential weight of the lane's line, one 80-byte record per lane
+  double lrec[64][10];
+  int32_t p;           // nodes per direction
+  // geometry in FP64 for the host-side table builders
+  double hd[3], detJd, cd, gamd[3];
   // Even-odd split of the tables (H = p / 2, middle index H when p is odd).
   // The nodes are symmetric about the cell centre, so the derivative matrix
   // is centro-antisymmetric and the face rows of side 1 are the mirror images
@@ -134,6 +153,9 @@ struct dg_mesh {
   dgi::ScalarArgs<float> pf[dgi::SP_COUNT]{};
   dgi::ScalarArgs<double>* d_pd = nullptr;
   dgi::ScalarArgs<float>* d_pf = nullptr;
+  uint32_t* d_blocks = nullptr;  // block tables of the apply and adjoint grids (2 words per block)
+  uint32_t* d_waves = nullptr;   // wave table of the matrix-core apply (2 words per wave)
+  int64_t nwaves = 0;             // its length
   int64_t gamma_off[3] = {0, 0, 0};
 };
 
@@ -150,6 +172,11 @@ hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipS
 // Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,
 // line weights) and uploads them to M.d_pd / M.d_pf (allocated by the caller).
 hipError_t scalar_params_upload(dg_mesh& M);
+// Matrix-core apply of the p = 4, FP64, kappa = 1 operator (variant SP_APPLY or SP_APPLY_T).
+bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa);
+hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, hipStream_t s);
+// Builds and uploads the wave table of the matrix-core apply (M.d_waves).
+hipError_t mfma_setup(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
 
 // Vector kernels of the solvers (deterministic fixed-order reductions).

@@ -68,33 +68,19 @@ struct Layout<8> {
   static constexpr int S1 = 9, S2 = 72, NP = 576;
 };
 
-// Bijective block renumbering: hardware block b runs on XCD b % 8; give each
-// XCD a contiguous range of logical blocks so its L2 holds the neighbours.
-__device__ __forceinline__ int xcd_swizzle(int b, int G) {
-  const int q = G >> 3, r = G & 7;
-  const int xcd = b & 7, idx = b >> 3;
-  return xcd * q + min(xcd, r) + idx;
-}
-
 struct BlockCoord {
-  int chunk, ey, ez;
+  int ex0, ey, ez;  // x index of the chunk's first cell, y and z of its row
 };
 
-// Logical block t -> (chunk, y, z) in the sweep order (slab, y, z in slab, chunk).
+// Coordinates of this hardware block's chunk (table built on the host: sweep
+// order, XCD-aware renumbering).
 template <typename T>
-__device__ __forceinline__ BlockCoord block_coord(int t, const ScalarArgs<T>& a) {
-  const int nc = a.nchunk, ny = a.n[1], nz = a.n[2], sz = a.sz;
-  const int per_slab = nc * ny * sz;
-  const int slab = t / per_slab;
-  const int rem = t - slab * per_slab;
-  const int hz = min(sz, nz - slab * sz);
-  const int ey = rem / (nc * hz);
-  const int rem2 = rem - ey * nc * hz;
-  const int ezi = rem2 / nc;
+__device__ __forceinline__ BlockCoord block_coord(const ScalarArgs<T>& a) {
+  const uint32_t w0 = a.blocks[2 * blockIdx.x], w1 = a.blocks[2 * blockIdx.x + 1];
   BlockCoord c;
-  c.chunk = rem2 - ezi * nc;
-  c.ey = ey;
-  c.ez = slab * sz + ezi;
+  c.ex0 = (int)(w0 & 0xffffu);
+  c.ey = (int)(w0 >> 16);
+  c.ez = (int)w1;
   return c;
 }
 
@@ -109,16 +95,22 @@ struct AdjCellsPerBlock {
   static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
 };
 
-// Copies nvalid contiguous cell blocks from global memory into the padded LDS layout.
-template <int P, typename T>
-__device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase, int nvalid,
-                                           int nthreads) {
+// Copies nvalid contiguous cells from global memory into the padded LDS
+// layout; NT threads, NT P^2 >= EB P^3 values, so each thread moves at most
+// ceil(EB P / NT') values (a compile-time count).
+template <int P, typename T, int EB, int NT>
+__device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase, int nvalid) {
   constexpr int N = P * P * P;
+  constexpr int K = (EB * N + NT - 1) / NT;
   using Ly = Layout<P>;
-  for (int i = threadIdx.x; i < nvalid * N; i += nthreads) {
-    const int le = i / N, l = i - le * N;
-    const int i2 = l / (P * P), i1 = (l / P) % P, i0 = l % P;
-    s[le * Ly::NP + i0 + Ly::S1 * i1 + Ly::S2 * i2] = g[gbase + i];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int i = threadIdx.x + k * NT;
+    if (i < nvalid * N) {
+      const int le = i / N, l = i - le * N;
+      const int i2 = l / (P * P), i1 = (l / P) % P, i0 = l % P;
+      s[le * Ly::NP + i0 + Ly::S1 * i1 + Ly::S2 * i2] = g[gbase + i];
+    }
   }
 }
 
@@ -331,9 +323,9 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
   __shared__ T sy[EB * Ly::NP];  // x-line results, then += y-line results
 
-  const BlockCoord bc = block_coord(xcd_swizzle(blockIdx.x, gridDim.x), a);
+  const BlockCoord bc = block_coord(a);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const int ex0 = bc.chunk * EB;
+  const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
   const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
   const uint32_t gbase = (row + ex0) * N;
@@ -346,8 +338,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const uint32_t nxy = (uint32_t)nx * ny;
   T nb1[2][P], nk1[2][P], nb2[2][P], nk2[2][P];
   bool has1[2], has2[2];
-  load_cells<P, T>(sx, x, gbase, nvalid, NT);
-  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
+  load_cells<P, T, EB, NT>(sx, x, gbase, nvalid);
+  if (KAPPA) load_cells<P, T, EB, NT>(sk, kappa, gbase, nvalid);
   __syncthreads();
 
   const T wt = a.wl[li];  // tangential weight w_ta w_tb of this thread's lines
@@ -535,15 +527,15 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
   __shared__ T sy0[EB * Ly::NP], sy1[EB * Ly::NP], sd0[EB * Ly::NP], sd1[EB * Ly::NP];
 
-  const BlockCoord bc = block_coord(xcd_swizzle(blockIdx.x, gridDim.x), a);
+  const BlockCoord bc = block_coord(a);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const int ex0 = bc.chunk * EB;
+  const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
   const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
   const uint32_t gbase = (row + ex0) * N;
-  load_cells<P, T>(sg, g, gbase, nvalid, NT);
-  load_cells<P, T>(su, u, gbase, nvalid, NT);
-  if (KAPPA) load_cells<P, T>(sk, kappa, gbase, nvalid, NT);
+  load_cells<P, T, EB, NT>(sg, g, gbase, nvalid);
+  load_cells<P, T, EB, NT>(su, u, gbase, nvalid);
+  if (KAPPA) load_cells<P, T, EB, NT>(sk, kappa, gbase, nvalid);
   __syncthreads();
   const int le = threadIdx.x / L;
   const int li = threadIdx.x - le * L;
@@ -704,6 +696,33 @@ hipError_t dispatch_load(const dg_mesh& M, const T* f, T* b, hipStream_t s) {
   return hipGetLastError();
 }
 
+// Hardware block b runs on XCD b % 8: give each XCD a contiguous range of
+// the sweep so that its L2 holds the neighbours its blocks read.
+int xcd_swizzle(int b, int G) {
+  const int q = G >> 3, r = G & 7;
+  const int xcd = b & 7, idx = b >> 3;
+  return xcd * q + std::min(xcd, r) + idx;
+}
+
+// Block table of a sweep grid (chunks of eb cells of every x-row, swept as
+// (slab of sz z-planes, y, z within the slab, chunk)), indexed by hardware block.
+std::vector<uint32_t> block_table(int nx, int ny, int nz, int eb, int sz) {
+  const int nc = (nx + eb - 1) / eb;
+  const int G = nc * ny * nz;
+  std::vector<uint32_t> tab(2 * (size_t)G);
+  const int per_slab = nc * ny * sz;
+  for (int b = 0; b < G; ++b) {
+    const int t = xcd_swizzle(b, G);
+    const int slab = t / per_slab, rem = t - slab * per_slab;
+    const int hz = std::min(sz, nz - slab * sz);
+    const int ey = rem / (nc * hz), rem2 = rem - ey * nc * hz;
+    const int ezi = rem2 / nc, chunk = rem2 - ezi * nc;
+    tab[2 * (size_t)b] = (uint32_t)(chunk * eb) | ((uint32_t)ey << 16);
+    tab[2 * (size_t)b + 1] = (uint32_t)(slab * sz + ezi);
+  }
+  return tab;
+}
+
 template <typename T>
 void fill_params(const ScalarArgs<T>& base, const Tables1D& tab, int p, ScalarArgs<T>* out) {
   for (int v = 0; v < SP_COUNT; ++v) {
@@ -727,6 +746,7 @@ void fill_params(const ScalarArgs<T>& base, const Tables1D& tab, int p, ScalarAr
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa, bool transpose,
                         hipStream_t s) {
   const int v = transpose ? SP_APPLY_T : SP_APPLY;
+  if (mfma_apply_supported(M, prec, kappa != nullptr)) return mfma_apply(M, v, (const double*)x, (double*)y, s);
   if (prec == DG_F64) return dispatch_apply<double>(M, v, (const double*)x, (double*)y, (const double*)kappa, s);
   return dispatch_apply<float>(M, v, (const float*)x, (float*)y, (const float*)kappa, s);
 }
@@ -748,7 +768,25 @@ hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipS
 hipError_t scalar_params_upload(dg_mesh& M) {
   fill_params(M.sd, M.tab, M.p, M.pd);
   fill_params(M.sf, M.tab, M.p, M.pf);
-  hipError_t e = hipMemcpy(M.d_pd, M.pd, sizeof(M.pd), hipMemcpyHostToDevice);
+  // block tables: apply grid, then adjoint grid
+  const std::vector<uint32_t> ta =
+      block_table(M.pd[SP_APPLY].n[0], M.pd[SP_APPLY].n[1], M.pd[SP_APPLY].n[2], apply_cells_per_block(M.p),
+                  M.pd[SP_APPLY].sz);
+  const std::vector<uint32_t> tj =
+      block_table(M.pd[SP_ADJOINT].n[0], M.pd[SP_ADJOINT].n[1], M.pd[SP_ADJOINT].n[2],
+                  adjoint_cells_per_block(M.p), M.pd[SP_ADJOINT].sz);
+  hipError_t e = hipMalloc(&M.d_blocks, sizeof(uint32_t) * (ta.size() + tj.size()));
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(M.d_blocks, ta.data(), sizeof(uint32_t) * ta.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  e = hipMemcpy(M.d_blocks + ta.size(), tj.data(), sizeof(uint32_t) * tj.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return e;
+  for (int v = 0; v < SP_COUNT; ++v) {
+    const uint32_t* t = v == SP_ADJOINT ? M.d_blocks + ta.size() : M.d_blocks;
+    M.pd[v].blocks = t;
+    M.pf[v].blocks = t;
+  }
+  e = hipMemcpy(M.d_pd, M.pd, sizeof(M.pd), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   return hipMemcpy(M.d_pf, M.pf, sizeof(M.pf), hipMemcpyHostToDevice);
 }

@@ -38,7 +38,7 @@ def test_validate_accepts_workload_descriptors(dg):
     (dict(nx=0), -1), (dict(k=0), -1), (dict(k=8), -2), (dict(m=7, k=3), -2), (dict(m=-1), -1),
     (dict(problem=5), -1), (dict(penalty_form=2), -1), (dict(dirichlet_mask=0x40), -1),
     (dict(kappa_mode=3), -1), (dict(alpha=-1.0), -1), (dict(theta=float("nan")), -1),
-    (dict(problem=1, k=1), -2), (dict(problem=1, kappa_mode=1), -1),
+    (dict(problem=1, k=1), -2), (dict(problem=1, kappa_mode=1), -1), (dict(nx=65536, ny=1, nz=1), -1),
 ])
 def test_validate_rejects(dg, kw, status):
     base = dict(nx=2, k=3)

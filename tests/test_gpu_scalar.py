@@ -53,6 +53,25 @@ def test_degrees_shapes_masks(gpu_lib, k, shape, theta, mask, c):
     assert relerr(y, ref) < TOL64
 
 
+@pytest.mark.parametrize("shape,theta,mask,c", [((6, 5, 4), 1.0, 0x2D, 0.7), ((9, 2, 3), -1.0, 0x3F, 1.0),
+                                                 ((5, 1, 2), -1.0, 0x12, 0.0), ((4, 4, 4), 1.0, 0x00, 1.5)])
+def test_q3_rows_and_sides(gpu_lib, shape, theta, mask, c):
+    """k = 3 (the matrix-core apply) with x-rows that end in a partial group
+    of cells, every mix of interior / Dirichlet / natural sides per direction,
+    both theta, with and without the mass term; forward and transposed."""
+    dg = gpu_lib
+    print(f"case: k=3 shape={shape} theta={theta} mask={mask:#x} c={c}", flush=True)
+    nx, ny, nz = shape
+    x = workloads.uniform(nx * ny * nz * 64, 4242 + nx)
+    desc = dg.make_desc(nx, ny, nz, k=3, c=c, theta=theta, dirichlet_mask=mask)
+    A = ScalarDG(Problem(nx, ny, nz, k=3, c=c, theta=theta, mask=mask)).assemble()
+    assert relerr(gpu_apply(dg, desc, x), A.matvec(x)) < TOL64
+    mesh = dg.Mesh(desc)
+    ATg, _ = mesh.apply_adjoint(torch.from_numpy(x).cuda(), want_dkappa=False)
+    torch.cuda.synchronize()
+    assert relerr(ATg.cpu().numpy(), A.rmatvec(x)) < TOL64
+
+
 @pytest.mark.parametrize("penalty_form", [0, 1])
 def test_penalty_forms(gpu_lib, penalty_form):
     dg = gpu_lib
