@@ -22,14 +22,19 @@
 //    direction chain through the accumulator. The matrices cost one VGPR
 //    pair each.
 //  * Each wavefront owns NC consecutive cells of an x-row and issues all of
-//    its loads first (own cells in the three line layouts, the x-line of
-//    the cells before and after, the y- and z-neighbour lines), so that many
-//    bytes are in flight per wavefront; the x-neighbour lines of interior
-//    cells are the wavefront's own loads. The wavefronts are independent:
-//    no block barriers.
+//    its global reads first: its cells once in natural node order (the z
+//    layout), the x-lines of the cells beyond both ends, and the y- and
+//    z-neighbour cells read directly in the layout they are used in (the
+//    y-layout read is a permutation inside each 512-byte cell). The x and y
+//    layouts of its own cells are formed with ds_bpermute (no LDS memory),
+//    and the x-neighbours of the inner cells are these same values. The
+//    wavefronts are independent: no barriers, no LDS allocation.
+//  * Per lane, the A-operand entries of the nine interior-cell operators and
+//    the line weight form one 80-byte record (five 16-byte reads); boundary
+//    cells read their own K variant.
 //  * The results of the x and y directions are brought to the natural node
-//    order with ds_bpermute and summed with the z result, which is already
-//    natural; the cell is written with one coalesced store.
+//    order with ds_bpermute and summed with the z result; one coalesced
+//    store per cell.
 //  * Wavefronts walk the sweep order (slab of z-planes, y, z, x-chunk) with
 //    an XCD-aware renumbering (table built on the host), so that the y- and
 //    z-neighbour lines are served by the XCD's L2.
@@ -42,7 +47,6 @@ namespace dgi {
 namespace {
 
 constexpr int NC = 4;            // cells per wavefront (consecutive along x)
-constexpr int NSLOT = 5 * NC + 2;  // LDS cells per wavefront: own, two x-ends, four neighbour groups
 constexpr int T_INT = 0, T_DIR = 1, T_NONE = 2;
 
 __device__ __forceinline__ double mfma(double a, double b, double c) {
@@ -58,37 +62,14 @@ __device__ __forceinline__ double lane_read(double v, int src) {
   return __builtin_bit_cast(double, r);
 }
 
-// orders this wavefront's LDS writes before its later reads by other lanes
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 __device__ __forceinline__ int side_type(bool has, bool dirichlet) {
   return has ? T_INT : (dirichlet ? T_DIR : T_NONE);
 }
 
-// Reads `ncell` consecutive cells starting at cell `c` as 16-byte pieces
-// (lane i takes pieces i and i + 64): one load instruction per two cells.
-__device__ __forceinline__ void load_group(double2* r, const double2* __restrict__ x2, uint32_t c, int ncell,
-                                           bool present, int lane) {
-#pragma unroll
-  for (int k = 0; k < NC / 2; ++k) {
-    const int i = lane + 64 * k;
-    r[k] = (present && i < 32 * ncell) ? x2[(size_t)c * 32 + i] : double2{0.0, 0.0};
-  }
-}
-__device__ __forceinline__ void store_group(double* s, const double2* r, int lane) {
-#pragma unroll
-  for (int k = 0; k < NC / 2; ++k) reinterpret_cast<double2*>(s)[lane + 64 * k] = r[k];
-}
-
-// One wavefront per block: LDS is released as soon as the wavefront ends.
+// One wavefront per block; the wavefronts are independent.
 __global__ void __launch_bounds__(64)
     k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
                     const uint32_t* __restrict__ waves) {
-  __shared__ double sb[NSLOT * 64];
   const ScalarArgs<double>& a = *ap;
   const int lane = threadIdx.x;
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
@@ -102,91 +83,64 @@ __global__ void __launch_bounds__(64)
   const uint32_t c0 = row + ex0;
   const bool hy0 = ey > 0, hy1 = ey < ny - 1, hz0 = ez > 0, hz1 = ez < nz - 1;
   const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
-  const double2* __restrict__ x2 = reinterpret_cast<const double2*>(x);
 
-  // this lane's operator entries (interior cell) and line weight
   double2 rec[5];
   const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
 #pragma unroll
   for (int k = 0; k < 5; ++k) rec[k] = lr[k];
-  // all global reads first: own cells, the x-neighbours beyond both ends,
-  // the y- and z-neighbour groups (each a run of consecutive cells)
-  double2 rown[NC / 2], ryl[NC / 2], ryr[NC / 2], rzl[NC / 2], rzr[NC / 2], rend;
-  load_group(rown, x2, c0, nvalid, true, lane);
-  {
-    const bool right = lane >= 32;
-    const bool ok = right ? hxr : hxl;
-    const uint32_t ce = right ? c0 + nvalid : c0 - 1;
-    rend = ok ? x2[(size_t)ce * 32 + (lane & 31)] : double2{0.0, 0.0};
-  }
-  load_group(ryl, x2, c0 - nx, nvalid, hy0, lane);
-  load_group(ryr, x2, c0 + nx, nvalid, hy1, lane);
-  load_group(rzl, x2, c0 - nxy, nvalid, hz0, lane);
-  load_group(rzr, x2, c0 + nxy, nvalid, hz1, lane);
-
-  // LDS slots: 0..NC-1 own, NC left end, NC+1 right end, then y-left, y-right,
-  // z-left, z-right groups of NC cells; natural node order inside a slot
-  constexpr int S_END = NC, S_YL = NC + 2, S_YR = 2 * NC + 2, S_ZL = 3 * NC + 2, S_ZR = 4 * NC + 2;
-  store_group(sb, rown, lane);
-  reinterpret_cast<double2*>(sb + S_END * 64)[lane] = rend;
-  store_group(sb + S_YL * 64, ryl, lane);
-  store_group(sb + S_YR * 64, ryr, lane);
-  store_group(sb + S_ZL * 64, rzl, lane);
-  store_group(sb + S_ZR * 64, rzr, lane);
-  wave_sync();
-
   // line layouts: lane = l + 16 q, node q along the direction, line l = t1 + 4 t2
-  // over the two tangential indices in increasing dimension order
   const int q = lane >> 4, l = lane & 15, t1 = l & 3, t2 = l >> 2;
   const int nxl = q + 4 * t1 + 16 * t2;  // natural index of the x-layout lane
   const int nyl = t1 + 4 * q + 16 * t2;  // y-layout (the z-layout is the natural order)
   const int i0 = lane & 3, i1 = (lane >> 2) & 3, i2 = lane >> 4;
   const int srcx = i1 + 4 * i2 + 16 * i0, srcy = i0 + 4 * i2 + 16 * i1;  // lanes holding node `lane`
+  const size_t b0 = (size_t)c0 * 64;
+  // global reads: own cells (natural order), x-ends (x layout), y-neighbours (y layout), z-neighbours
+  double uz[NC], xl, xr, uyl[NC], uyr[NC], uzl[NC], uzr[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) uz[k] = k < nvalid ? x[b0 + 64 * k + lane] : 0.0;
+  xl = hxl ? x[b0 - 64 + nxl] : 0.0;
+  xr = hxr ? x[b0 + 64 * nvalid + nxl] : 0.0;
+#pragma unroll
+  for (int k = 0; k < NC; ++k) {
+    uyl[k] = (k < nvalid && hy0) ? x[b0 - (size_t)nx * 64 + 64 * k + nyl] : 0.0;
+    uyr[k] = (k < nvalid && hy1) ? x[b0 + (size_t)nx * 64 + 64 * k + nyl] : 0.0;
+    uzl[k] = (k < nvalid && hz0) ? x[b0 - (size_t)nxy * 64 + 64 * k + lane] : 0.0;
+    uzr[k] = (k < nvalid && hz1) ? x[b0 + (size_t)nxy * 64 + 64 * k + lane] : 0.0;
+  }
   const int ai = 4 * (lane & 3) + (lane >> 4);  // A operand: entry (lane % 4, lane / 16)
-
   const uint32_t mask = a.mask;
   const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
   double Kx_int = rec[0].x, Lx = rec[0].y, Rx = rec[1].x, Ky = rec[1].y, Ly = rec[2].x, Ry = rec[2].y;
   double Kz = rec[3].x, Lz = rec[3].y, Rz = rec[4].x;
-  const double wt = rec[4].y;  // tangential weight of the lane's line
-  if (vy != 0) Ky = a.Km[1][vy][ai];  // boundary rows and columns: other own-cell face terms
+  const double wt = rec[4].y;
+  if (vy != 0) Ky = a.Km[1][vy][ai];
   if (vz != 0) Kz = a.Km[2][vz][ai];
-
-  double out[NC];
+  // own cells in the x layout (the x-neighbours of the inner cells)
+  double ux[NC];
+#pragma unroll
+  for (int k = 0; k < NC; ++k) ux[k] = lane_read(uz[k], nxl);
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
-    out[k] = 0.0;
     if (k < nvalid) {
       const int ex = ex0 + k;
       const bool hx0 = ex > 0, hx1 = ex < nx - 1;
-      const int sl = k == 0 ? S_END : k - 1;
-      const int sr = k == nvalid - 1 ? S_END + 1 : k + 1;
+      const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
+      const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
       double Kx = Kx_int;
       if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
-      double cx = mfma(Kx, sb[k * 64 + nxl], 0.0);
-      if (hx0) cx = mfma(Lx, sb[sl * 64 + nxl], cx);
-      if (hx1) cx = mfma(Rx, sb[sr * 64 + nxl], cx);
-      double cy = mfma(Ky, sb[k * 64 + nyl], 0.0);
-      if (hy0) cy = mfma(Ly, sb[(S_YL + k) * 64 + nyl], cy);
-      if (hy1) cy = mfma(Ry, sb[(S_YR + k) * 64 + nyl], cy);
-      double cz = mfma(Kz, sb[k * 64 + lane], 0.0);
-      if (hz0) cz = mfma(Lz, sb[(S_ZL + k) * 64 + lane], cz);
-      if (hz1) cz = mfma(Rz, sb[(S_ZR + k) * 64 + lane], cz);
-      out[k] = lane_read(wt * cx, srcx) + lane_read(wt * cy, srcy) + wt * cz;
+      double cx = mfma(Kx, ux[k], 0.0);
+      if (hx0) cx = mfma(Lx, ul, cx);
+      if (hx1) cx = mfma(Rx, ur, cx);
+      double cy = mfma(Ky, lane_read(uz[k], nyl), 0.0);
+      if (hy0) cy = mfma(Ly, uyl[k], cy);
+      if (hy1) cy = mfma(Ry, uyr[k], cy);
+      double cz = mfma(Kz, uz[k], 0.0);
+      if (hz0) cz = mfma(Lz, uzl[k], cz);
+      if (hz1) cz = mfma(Rz, uzr[k], cz);
+      y[b0 + 64 * k + lane] = lane_read(wt * cx, srcx) + lane_read(wt * cy, srcy) + wt * cz;
     }
-  }
-  // results through the z-left slots (read above) and out as 16-byte pieces
-  wave_sync();
-#pragma unroll
-  for (int k = 0; k < NC; ++k) sb[(S_ZL + k) * 64 + lane] = out[k];
-  wave_sync();
-  double2* __restrict__ y2 = reinterpret_cast<double2*>(y);
-  const double2* so = reinterpret_cast<const double2*>(sb + S_ZL * 64);
-#pragma unroll
-  for (int k = 0; k < NC / 2; ++k) {
-    const int i = lane + 64 * k;
-    if (i < 32 * nvalid) y2[(size_t)c0 * 32 + i] = so[i];
   }
 }
 
@@ -211,33 +165,22 @@ hipError_t mfma_setup(dg_mesh& M) {
   if (W > 0x7fffffff / 2) return hipErrorInvalidValue;
   const int sz = nz >= 8 ? nz / 8 : 1;
   const int per_slab = nc * ny * sz;
-  constexpr int WAVES = 1;  // wavefronts per block
-  const int G = (int)((W + WAVES - 1) / WAVES);
-  std::vector<uint32_t> tab(2 * (size_t)G * WAVES, 0);
-  // logical wavefront t = chunk + nc (z in slab + hz y) + per_slab slab; hardware
-  // wavefront WAVES b + v runs logical wavefront WAVES swizzle(b) + v
+  // logical wavefront t = chunk + nc (z in slab + hz y) + per_slab slab;
+  // hardware block b (one wavefront) runs logical wavefront swizzle(b)
+  const int G = (int)W;
+  std::vector<uint32_t> tab(2 * (size_t)G, 0);
   for (int b = 0; b < G; ++b) {
-    const int lb = xcd_swizzle_host(b, G);
-    for (int v = 0; v < WAVES; ++v) {
-      const int64_t t = (int64_t)lb * WAVES + v;
-      const size_t hw = (size_t)b * WAVES + v;
-      if (t >= W) {
-        // past the end of the sweep: x index 65535 >= nx, so the wavefront has no cells
-        tab[2 * hw] = 0xffffu;
-        tab[2 * hw + 1] = 0;
-        continue;
-      }
-      const int slab = (int)(t / per_slab), rem = (int)(t - (int64_t)slab * per_slab);
-      const int hz = std::min(sz, nz - slab * sz);
-      const int ey = rem / (nc * hz), rem2 = rem - ey * nc * hz;
-      const int ezi = rem2 / nc, chunk = rem2 - ezi * nc;
-      tab[2 * hw] = (uint32_t)(chunk * NC) | ((uint32_t)ey << 16);
-      tab[2 * hw + 1] = (uint32_t)(slab * sz + ezi);
-    }
+    const int t = xcd_swizzle_host(b, G);
+    const int slab = t / per_slab, rem = t - slab * per_slab;
+    const int hz = std::min(sz, nz - slab * sz);
+    const int ey = rem / (nc * hz), rem2 = rem - ey * nc * hz;
+    const int ezi = rem2 / nc, chunk = rem2 - ezi * nc;
+    tab[2 * (size_t)b] = (uint32_t)(chunk * NC) | ((uint32_t)ey << 16);
+    tab[2 * (size_t)b + 1] = (uint32_t)(slab * sz + ezi);
   }
   hipError_t e = hipMalloc(&M.d_waves, sizeof(uint32_t) * tab.size());
   if (e != hipSuccess) return e;
-  M.nwaves = (int64_t)G * WAVES;
+  M.nwaves = G;
   return hipMemcpy(M.d_waves, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
 }
 

@@ -154,7 +154,7 @@ struct dg_mesh {
   dgi::ScalarArgs<double>* d_pd = nullptr;
   dgi::ScalarArgs<float>* d_pf = nullptr;
   uint32_t* d_blocks = nullptr;  // block tables of the apply and adjoint grids (2 words per block)
-  uint32_t* d_waves = nullptr;   // wave table of the matrix-core apply (2 words per wave)
+  uint32_t* d_waves = nullptr;   // wavefront table of the matrix-core apply (2 words per wavefront)
   int64_t nwaves = 0;             // its length
   int64_t gamma_off[3] = {0, 0, 0};
 };
@@ -175,7 +175,7 @@ hipError_t scalar_params_upload(dg_mesh& M);
 // Matrix-core apply of the p = 4, FP64, kappa = 1 operator (variant SP_APPLY or SP_APPLY_T).
 bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa);
 hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, hipStream_t s);
-// Builds and uploads the wave table of the matrix-core apply (M.d_waves).
+// Builds and uploads the wavefront table of the matrix-core apply (M.d_waves).
 hipError_t mfma_setup(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
 
