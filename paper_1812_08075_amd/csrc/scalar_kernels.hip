@@ -197,29 +197,28 @@ __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb
     for (int q = 0; q < H; ++q) om = fma(a.G2c[q], ro[q], om);
   }
   // own traces and reference-coordinate derivatives at both ends: side 1 uses
-  // the mirror image of the side-0 rows (the derivative row with a sign)
-  T ae = ODD ? a.Eh * vm : T(0), bo = T(0), pe = ODD ? a.DEh * vm : T(0), qo = T(0);
+  // the mirror image of the side-0 rows (the derivative row with a sign). They
+  // are formed exactly as the neighbour across that face forms them (same rows,
+  // same order), so both cells see bitwise the same face values and the
+  // discrete operator stays symmetric in floating point (theta = -1).
+  T uT[2] = {T(0), T(0)}, dT[2] = {T(0), T(0)};
 #pragma unroll
-  for (int j = 0; j < H; ++j) {
-    ae = fma(a.Ep[j], ve[j], ae);
-    bo = fma(a.Em[j], vo[j], bo);
-    pe = fma(a.DEp[j], ve[j], pe);
-    qo = fma(a.DEm[j], vo[j], qo);
+  for (int j = 0; j < P; ++j) {
+    uT[0] = fma(a.e[0][j], v[j], uT[0]);
+    dT[0] = fma(a.de[0][j], v[j], dT[0]);
+    uT[1] = fma(a.e[0][P - 1 - j], v[j], uT[1]);
+    dT[1] = fma(a.de[0][P - 1 - j], v[j], dT[1]);
   }
-  const T uT[2] = {ae + bo, ae - bo};
-  // outward normal derivative = -(1/h) dT (the -1/h sits in fAh)
-  const T dT[2] = {pe + qo, pe - qo};
+  // (outward normal derivative = -(1/h) dT; the -1/h sits in fAh)
   const bool face_kappa = KAPPA && !a.kappa_face_one;
   T kT[2] = {T(1), T(1)};
   if (face_kappa) {
-    T ka = ODD ? a.Eh * kv[H] : T(0), kb = T(0);
+    kT[0] = kT[1] = T(0);
 #pragma unroll
-    for (int j = 0; j < H; ++j) {
-      ka = fma(a.Ep[j], ks[j], ka);
-      kb = fma(a.Em[j], kd[j], kb);
+    for (int j = 0; j < P; ++j) {
+      kT[0] = fma(a.e[0][j], kv[j], kT[0]);
+      kT[1] = fma(a.e[0][P - 1 - j], kv[j], kT[1]);
     }
-    kT[0] = ka + kb;
-    kT[1] = ka - kb;
   }
   // face fluxes: Rv multiplies the trace row of side s, Sd (times fB0) its derivative row
   T Rv[2], Sd[2];
