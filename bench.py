@@ -2,11 +2,13 @@
 
 One step = one matrix-free FP64 application y = A x of the Q3 SIPG
 diffusion-reaction operator on the 64^3 axis-aligned mesh (16,777,216 DOFs),
-inputs resident in HBM. The JSON line reports DOFs/s of that step, the
-roofline of the apply kernel (HBM-bound: 16 B/DOF compulsory traffic) and the
-CPU oracle's block-sparse SpMV as a baseline; `extra` carries the other
-workloads (FP32 apply, kappa apply and adjoint, Q5 applies, Stokes, the
-FP64-CG vs FP32-refinement solve) each timed the same way.
+inputs resident in HBM; the step runs the matrix-core kernel k_apply_q3_mfma.
+The JSON line reports DOFs/s of that step, the roofline of the apply kernel
+(HBM-bound: 16 B/DOF compulsory traffic), the achieved bandwidth of a plain
+device copy on the same box, and the CPU oracle's block-sparse SpMV as a
+baseline; `extra` carries the other workloads (cold-buffer apply, FP32 apply,
+kappa apply and adjoint, Q5 applies, Stokes, the FP64-CG vs FP32-refinement
+solve) each timed the same way.
 """
 from __future__ import annotations
 
@@ -289,8 +291,8 @@ def main():
                    "penalty": "3k(k+1)/h", "theta": -1.0, "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": r64["hbm_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": r64["hbm_frac"],
-                     "traffic": measured_traffic("scalar_kernels.hip", "k_scalar_apply_q3_64cube_f64"),
-                     "kernel": "k_scalar_apply<4,double,false>",
+                     "traffic": measured_traffic("apply_mfma.hip", "k_apply_q3_mfma_64cube_f64"),
+                     "kernel": "k_apply_q3_mfma",
                      "algorithmic_bytes_per_launch": info.bytes_apply[0],
                      "fp64_flop_frac": r64["flop_frac"]},
         "extra": extra,

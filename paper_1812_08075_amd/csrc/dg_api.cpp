@@ -325,6 +325,8 @@ dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out) 
       }
       M->tab = dgi::make_tables(M->p, M->m);
       hip_check(hipGetDevice(&M->device), "hipGetDevice");
+      hip_check(hipDeviceGetAttribute(&M->num_cu, hipDeviceAttributeMultiprocessorCount, M->device),
+                "hipDeviceGetAttribute");
       fill_scalar_args(*M, M->sd);
       fill_scalar_args(*M, M->sf);
       if (desc->problem == DG_PROBLEM_DIFFREAC) {

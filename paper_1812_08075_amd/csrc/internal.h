@@ -141,6 +141,7 @@ struct dg_mesh {
   int64_t nelem = 0, N = 0, ndofs = 0, nqp = 0;
   bool axis_aligned = true;
   int device = 0;
+  int num_cu = 0;                 // compute units of the device
   dgi::Tables1D tab;
   dgi::ScalarArgs<double> sd{};
   dgi::ScalarArgs<float> sf{};
