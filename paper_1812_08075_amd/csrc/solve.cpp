@@ -17,6 +17,7 @@
 //
 // Convergence is declared on the true FP64 residual |b - A x| <= rtol |b| in
 // every mode.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <string>
@@ -189,6 +190,9 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     ck(dgi::blas_copy(rl.p, pl.p, DG_F32, n, s), "p = r");
     ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
     double last = std::sqrt(S.read().rr);
+    double lowest = last;  // smallest recursive residual since the last correction
+    double prev = last;    // recursive residual at the previous check
+    int growth = 0;        // consecutive checks with a growing residual
     int total = 0, outer = 0, since_restart = 0;
     while (res > target && total < prm->maxit && !breakdown) {
       for (int it = 0; it < check && total < prm->maxit; ++it, ++total, ++since_restart) {
@@ -198,17 +202,28 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
         ck(dgi::blas_xpay(rl.p, pl.p, DG_F32, n, S.st(), s), "p update");
       }
       const dgi::CgState h = S.read();
-      // A non-positive p.Ap in the FP32 recursion (its residual has drifted below
-      // FP32 accuracy) triggers a correction with a fresh search direction; a
-      // breakdown right after such a restart is a real one.
-      const bool lost = h.breakdown != 0;
-      if (lost && since_restart <= check) {
+      const double cur = std::sqrt(h.rr);
+      // The FP32 recursion can lose its footing once its residual has drifted
+      // below FP32 accuracy: p.Ap turns non-positive, or, with p.Ap still
+      // positive, the recursive residual starts to grow geometrically. Either
+      // triggers a correction with a fresh search direction; a loss right after
+      // such a restart is a real breakdown.
+      // (CG residuals are not monotone and spike briefly: growth counts only
+      // when it has lasted three check windows in a row and exceeds a factor 4
+      // over the lowest value since the last correction)
+      growth = cur > prev ? growth + 1 : 0;
+      prev = cur;
+      const bool diverging = !std::isfinite(cur) || (growth >= 3 && cur > 4.0 * lowest);
+      const bool lost = h.breakdown != 0 || diverging;
+      lowest = std::min(lowest, cur);
+      if (h.breakdown != 0 && since_restart <= check) {
         breakdown = 1;
         break;
       }
-      const double cur = std::sqrt(h.rr);
       if (lost || cur <= RU_DROP * last || cur <= target || total >= prm->maxit) {
-        ck(dgi::blas_accumulate(x, (float*)xl.p, n, s), "x += xl");
+        // a non-finite FP32 iterate is dropped rather than added
+        if (std::isfinite(cur)) ck(dgi::blas_accumulate(x, (float*)xl.p, n, s), "x += xl");
+        else ck(dgi::blas_zero(xl.p, DG_F32, n, s), "xl = 0");
         ++outer;
         res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
         if (res <= target) break;
@@ -219,7 +234,8 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
           since_restart = 0;
         }
         ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
-        last = std::sqrt(S.read().rr);
+        last = lowest = prev = std::sqrt(S.read().rr);
+        growth = 0;
       }
     }
     info->iterations = total;

@@ -104,6 +104,21 @@ def test_refinement_survives_fp32_breakdown(gpu_lib, drop):
     assert st == dg.DG_OK and info.rel_residual <= 1e-10
 
 
+@pytest.mark.parametrize("drop", [0.03, 1e-3])
+def test_refinement_small_drop_at_scale(gpu_lib, drop):
+    """The Q5 40^3 solve with corrections far apart: the FP32 recursion loses
+    its footing (its residual grows while p.Ap stays positive); the solve
+    restarts from the true residual and converges instead of diverging."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    print(f"case: RU drop {drop} Q5 40^3", flush=True)
+    mesh, b = setup(dg, w, w.n)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 2, b, x, rtol=1e-10, inner_rtol=drop, maxit=30000, check_every=20)
+    print(f"its={info.iterations} outer={info.outer} res={info.rel_residual:.2e}", flush=True)
+    assert st == dg.DG_OK and info.rel_residual <= 1e-10
+
+
 def test_not_converged_reported(gpu_lib):
     dg = gpu_lib
     mesh, b = setup(dg, workloads.WORKLOADS[5], 3)
