@@ -212,6 +212,62 @@ void dgi::derive_face_constants(ScalarArgs<T>& a) {
   // 1D line operators (kappa = 1), in long double from the FP64 geometry
   using ld = long double;
   const int p = a.p;
+  {
+    // any degree: even/odd interior K, rank-2 neighbour rows, boundary corrections
+    const ld cc = (ld)(double)a.c_cons, cs = (ld)(double)a.c_sym;
+    const int H = p / 2;
+    for (int d = 0; d < 3; ++d) {
+      dgi::LineOp<T>& o = a.lo[d];
+      const ld h = a.hd[d], detJ = a.detJd;
+      const ld vs = detJ / (h * h), fs = detJ / h;
+      const ld fA = fs * cc / 2, fG = fs * (ld)a.gamd[d];
+      const ld fB[2] = {-fs * cs / 2 / h, fs * cs / 2 / h};
+      ld e[2][dgi::PMAX], de[2][dgi::PMAX], nrm[2][dgi::PMAX];
+      for (int s = 0; s < 2; ++s)
+        for (int j = 0; j < p; ++j) {
+          e[s][j] = (ld)(double)a.e[s][j];
+          de[s][j] = (ld)(double)a.de[s][j];
+          nrm[s][j] = (s ? 1 : -1) * de[s][j] / h;
+        }
+      ld K[dgi::PMAX][dgi::PMAX];
+      for (int i = 0; i < p; ++i)
+        for (int j = 0; j < p; ++j) {
+          ld acc = 0;
+          for (int q = 0; q < p; ++q)
+            acc += (ld)(double)a.D[q * p + i] * vs * (ld)(double)a.w[q] * (ld)(double)a.D[q * p + j];
+          if (d == 0 && i == j) acc += (ld)a.cd * detJ * (ld)(double)a.w[i];
+          for (int s = 0; s < 2; ++s)
+            acc += fA * e[s][i] * nrm[s][j] + fG * e[s][i] * e[s][j] + fB[s] * de[s][i] * e[s][j];
+          K[i][j] = acc;
+        }
+      for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < H; ++j) {
+          o.Kp[i * H + j] = (T)((K[i][j] + K[i][p - 1 - j]) / 2);
+          o.Km[i * H + j] = (T)((K[i][j] - K[i][p - 1 - j]) / 2);
+        }
+        if (p & 1) {
+          o.Kc[i] = (T)K[i][H];
+          o.Kr[i] = (T)K[H][i];
+        }
+      }
+      o.Kh = (T)((p & 1) ? K[H][H] : 0);
+      for (int j = 0; j < p; ++j) {
+        o.la[j] = (T)(-fA * nrm[1][j] - fG * e[1][j]);
+        o.lb[j] = (T)(-fB[0] * e[1][j]);
+      }
+      for (int s = 0; s < 2; ++s) {
+        const ld sg = s ? 1 : -1;
+        // Dirichlet: the one-sided consistency and symmetry terms count twice
+        o.bq[0][s][0] = (T)(fA * sg / h);
+        o.bq[0][s][1] = (T)0;
+        o.bq[0][s][2] = (T)fB[s];
+        // natural: no face terms at all
+        o.bq[1][s][0] = (T)(-fA * sg / h);
+        o.bq[1][s][1] = (T)(-fG);
+        o.bq[1][s][2] = (T)(-fB[s]);
+      }
+    }
+  }
   if (p == 4) {
     const ld cc = (ld)(double)a.c_cons, cs = (ld)(double)a.c_sym;
     for (int d = 0; d < 3; ++d) {

@@ -43,6 +43,25 @@ struct EvenOdd {
   T fB0;               // |F| c_sym / 2 (-1/h): symmetry term of side 0
 };
 
+// 1D line operator of one direction for kappa = 1, any degree (see
+// ScalarArgs::lo): out = K u + L u_left + R u_right along a line.
+template <typename T>
+struct LineOp {
+  // interior K (both sides interior) is centro-symmetric: even/odd blocks
+  T Kp[HMAX * HMAX];  // [i H + j] (K_ij + K_i,p-1-j) / 2
+  T Km[HMAX * HMAX];  // [i H + j] (K_ij - K_i,p-1-j) / 2
+  T Kc[HMAX];         // K_iH (odd p)
+  T Kr[HMAX];         // K_Hj (odd p)
+  T Kh;               // K_HH (odd p)
+  // L = e0 la^T + de0 lb^T (rank 2); R = e1 ra^T + de1 rb^T with ra, rb the
+  // mirror images of la, -lb
+  T la[PMAX], lb[PMAX];
+  // own-cell correction of K on a boundary side s of type t (0 Dirichlet,
+  // 1 natural): e_s (cn d_s.u + ce e_s.u) + de_s (cb e_s.u), d_s = reference
+  // derivative row of side s
+  T bq[2][2][3];      // [t][s] {cn, ce, cb}
+};
+
 // Parameter block of the axis-aligned diffusion-reaction kernels. It lives in
 // device memory (one copy per precision and kernel variant, written once at
 // mesh creation) and the kernels take a pointer to it: every lane uses the
@@ -88,6 +107,7 @@ struct alignas(16) ScalarArgs {
   // d = 0) and the own-cell face terms, L and R the neighbour face terms.
   // K has one variant per pair of side types (interior, Dirichlet, none):
   // index 3 t0 + t1. Row-major 4 x 4.
+  LineOp<T> lo[3];     // per direction, kappa = 1
   T Km[3][9][16];
   T Lm[3][16];
   T Rm[3][16];

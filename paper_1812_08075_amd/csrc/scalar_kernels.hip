@@ -263,6 +263,104 @@ __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb
   if (ODD) out[H] = om;
 }
 
+// kappa = 1: the line's result is K u + L u_left + R u_right with the 1D
+// line operators of ScalarArgs::lo (volume, mass for the x lines, and the
+// SIPG face terms of both ends, built on the host). The interior K is
+// centro-symmetric and applied in even/odd form; L and R have rank 2 (the
+// neighbour's trace and normal derivative at the shared face), and a boundary
+// side adds a rank-2 correction of K. The neighbour line is zero where there
+// is none; the tangential weight is applied by the caller.
+template <int P, typename T, int DIR>
+__device__ __forceinline__ void line_apply_const(const T* v, const T (*nb)[P], const bool* has_nb,
+                                                 const ScalarArgs<T>& a, T* out) {
+  constexpr int H = P / 2;
+  constexpr bool ODD = (P & 1) != 0;
+  const LineOp<T>& o = a.lo[DIR];
+  T ve[H], vo[H];
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    ve[j] = v[j] + v[P - 1 - j];
+    vo[j] = v[j] - v[P - 1 - j];
+  }
+  const T vm = ODD ? v[H] : T(0);
+  T oe[H], oo[H];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    T t0 = ODD ? o.Kc[i] * vm : T(0), t1 = T(0);
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+      t0 = fma(o.Kp[i * H + j], ve[j], t0);
+      t1 = fma(o.Km[i * H + j], vo[j], t1);
+    }
+    oe[i] = t0;
+    oo[i] = t1;
+  }
+  T om = T(0);
+  if (ODD) {
+    om = o.Kh * vm;
+#pragma unroll
+    for (int j = 0; j < H; ++j) om = fma(o.Kr[j], ve[j], om);
+  }
+  // coefficients of e0, de0 (side 0) and e1, de1 (side 1)
+  T A0 = T(0), B0 = T(0), A1 = T(0), B1 = T(0);
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    A0 = fma(o.la[j], nb[0][j], A0);
+    B0 = fma(o.lb[j], nb[0][j], B0);
+    A1 = fma(o.la[P - 1 - j], nb[1][j], A1);
+    B1 = fma(o.lb[P - 1 - j], nb[1][j], B1);
+  }
+  B1 = -B1;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (!has_nb[s]) {
+      const int t = ((a.mask >> (2 * DIR + s)) & 1u) ? 0 : 1;
+      T ev = T(0), dv = T(0);
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const int r = s ? P - 1 - j : j;
+        ev = fma(a.e[0][r], v[j], ev);
+        dv = fma(a.de[0][r], v[j], dv);
+      }
+      if (s) dv = -dv;
+      const T q1 = fma(o.bq[t][s][0], dv, o.bq[t][s][1] * ev), q2 = o.bq[t][s][2] * ev;
+      if (s == 0) {
+        A0 += q1;
+        B0 += q2;
+      } else {
+        A1 += q1;
+        B1 += q2;
+      }
+    }
+  }
+  const T cE = A0 + A1, cO = A0 - A1, dE = B0 - B1, dO = B0 + B1;
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    oe[i] = fma(cE, a.Ep[i], fma(dE, a.DEp[i], oe[i]));
+    oo[i] = fma(cO, a.Em[i], fma(dO, a.DEm[i], oo[i]));
+  }
+  if (ODD) om = fma(cE, a.Eh, fma(dE, a.DEh, om));
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    out[i] = oe[i] + oo[i];
+    out[P - 1 - i] = oe[i] - oo[i];
+  }
+  if (ODD) out[H] = om;
+}
+
+// The line work of direction DIR: line operators for kappa = 1 in FP64, the
+// general form otherwise (FP32 keeps the form whose face values are bitwise
+// the same on both sides of a face).
+template <int P, typename T, bool KAPPA, int DIR>
+__device__ __forceinline__ void line_work(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
+                                          const bool* has_nb, const ScalarArgs<T>& a, bool mass, T* out) {
+  if constexpr (!KAPPA && sizeof(T) == 8) {
+    line_apply_const<P, T, DIR>(v, nb, has_nb, a, out);
+  } else {
+    line_apply<P, T, KAPPA, DIR>(v, kv, nb, nk, has_nb, a, mass, out);
+  }
+}
+
 // Reads the line of direction DIR at (ta, tb) of LDS cell block `sc`.
 template <int P, typename T, int DIR>
 __device__ __forceinline__ void lds_line(const T* __restrict__ sc, int ta, int tb, T* v) {
@@ -354,13 +452,13 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     if (KAPPA) lds_line<P, T, 0>(ske, ta, tb, kv);
     neighbor_lines<P, T, 0>(sx, x, e, le, nvalid, ex, nx, 1u, ta, tb, nb, has);
     if (KAPPA) neighbor_lines<P, T, 0>(sk, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, nk, has);
-    line_apply<P, T, KAPPA, 0>(v, kv, nb, nk, has, a, true, out0);
+    line_work<P, T, KAPPA, 0>(v, kv, nb, nk, has, a, true, out0);
     // lines along y: (i0, i2) = (ta, tb)
     lds_line<P, T, 1>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
     neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb1, has1);
     if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk1, has1);
-    line_apply<P, T, KAPPA, 1>(v, kv, nb1, nk1, has1, a, false, out1);
+    line_work<P, T, KAPPA, 1>(v, kv, nb1, nk1, has1, a, false, out1);
 #pragma unroll
     for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
   }
@@ -377,7 +475,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
     neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb2, has2);
     if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk2, has2);
-    line_apply<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
+    line_work<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
   }
   __syncthreads();
   if (active) {
