@@ -205,7 +205,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--solve", action="store_true", help="include the Q5 solve comparison")
+    ap.add_argument("--no-solve", action="store_true",
+                    help="skip the Q5 40^3 FP64-CG vs FP32-refinement solve comparison")
     ap.add_argument("--only", choices=["stokes", "q4", "q5", "f32"], default=None,
                     help="run one secondary workload only (for profiling), no JSON line")
     ap.add_argument("--copy-probe", action="store_true",
@@ -271,7 +272,7 @@ def main():
         log("Q4 FP64 adjoint (A^T g and dL/dkappa)")
         extra["adjoint_q4_kappa_f64"] = bench_adjoint(dg, w4, args.steps, args.warmup)
         del m4, m5
-    if args.solve:
+    if not args.no_solve and not args.no_extra:
         extra["solve_q5_40cube"] = bench_solve(dg)
 
     out = {
