@@ -622,7 +622,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   __shared__ T sg[EB * Ly::NP];
   __shared__ T su[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
-  __shared__ T sy0[EB * Ly::NP], sy1[EB * Ly::NP], sd0[EB * Ly::NP], sd1[EB * Ly::NP];
+  __shared__ T sy[EB * Ly::NP], sd[EB * Ly::NP];  // x-line results, then += y-line results
 
   const BlockCoord bc = block_coord(a);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -639,40 +639,46 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
   const T wt = a.wl[li];
-  T og2[P], ok2[P];
+  const int ex = ex0 + le;
+  const uint32_t e = row + ex;
+  const T* sge = sg + le * Ly::NP;
+  const T* sue = su + le * Ly::NP;
+  const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
+  // lines along x: each node is written by exactly one thread
   if (active) {
-    const int ex = ex0 + le;
-    const uint32_t e = row + ex;
-    const T* sge = sg + le * Ly::NP;
-    const T* sue = su + le * Ly::NP;
-    const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
     T og[P], ok[P];
     adjoint_direction<P, T, KAPPA, 0>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, wt,
                                       a, true, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      sy0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = og[i];
-      sd0[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = ok[i];
+      sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = og[i];
+      sd[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = ok[i];
     }
+  }
+  __syncthreads();
+  // lines along y are added in place (again one thread per node); lines along z stay in registers
+  T og2[P], ok2[P];
+  if (active) {
+    T og[P], ok[P];
     adjoint_direction<P, T, KAPPA, 1>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ey, ny,
                                       (uint32_t)nx, ta, tb, wt, a, false, og, ok);
 #pragma unroll
     for (int i = 0; i < P; ++i) {
-      sy1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = og[i];
-      sd1[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] = ok[i];
+      const int o = le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
+      sy[o] += og[i];
+      sd[o] += ok[i];
     }
     adjoint_direction<P, T, KAPPA, 2>(sge, sue, ske, sg, su, sk, g, u, kappa, e, le, nvalid, bc.ez, nz,
                                       (uint32_t)nx * ny, ta, tb, wt, a, false, og2, ok2);
   }
   __syncthreads();
   if (active) {
-    const uint32_t e = row + ex0 + le;
     const int lo = le * Ly::NP + ta + Ly::S1 * tb;
     const uint32_t go = e * N + ta + P * tb;
 #pragma unroll
     for (int j = 0; j < P; ++j) {
-      ATg[go + j * L] = sy0[lo + j * Ly::S2] + sy1[lo + j * Ly::S2] + og2[j];
-      dkappa[go + j * L] = sd0[lo + j * Ly::S2] + sd1[lo + j * Ly::S2] + ok2[j];
+      ATg[go + j * L] = sy[lo + j * Ly::S2] + og2[j];
+      dkappa[go + j * L] = sd[lo + j * Ly::S2] + ok2[j];
     }
   }
 }

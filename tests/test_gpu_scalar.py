@@ -133,6 +133,19 @@ def test_q3_64cube_full_vector(gpu_lib):
     assert relerr(y, ref) < TOL64
 
 
+def test_q5_40cube_full_vector(gpu_lib):
+    """The Q5 40^3 solve workload (13.8M DOFs) at full size, FP64 (line-operator
+    kernel) and FP32 (sum-factorized kernel), against the oracle's deduplicated BSR."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    print("case: Q5 40^3 full size", flush=True)
+    x = workloads.inputs(w, "x")
+    ref = ScalarDG(problem_from_workload(w)).assemble("dedup").matvec(x)
+    desc = dg.desc_from_workload(w)
+    assert relerr(gpu_apply(dg, desc, x), ref) < TOL64
+    assert relerr(gpu_apply(dg, desc, x, dtype=torch.float32), ref) < TOL32
+
+
 def test_transposed_apply(gpu_lib):
     """A^T g with the non-symmetric variant (theta = +1), no dkappa."""
     dg = gpu_lib
