@@ -95,23 +95,19 @@ struct AdjCellsPerBlock {
   static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
 };
 
-// Copies nvalid contiguous cells from global memory into the padded LDS
-// layout; NT threads, NT P^2 >= EB P^3 values, so each thread moves at most
-// ceil(EB P / NT') values (a compile-time count).
-template <int P, typename T, int EB, int NT>
-__device__ __forceinline__ void load_cells(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase, int nvalid) {
-  constexpr int N = P * P * P;
-  constexpr int K = (EB * N + NT - 1) / NT;
+// Copies the calling thread's share of its cell into the padded LDS layout:
+// the thread that owns the lines (ta, tb) of cell le moves the P nodes
+// (ta, tb, 0..P-1), one z-plane apart. Per load the lanes of a cell read one
+// contiguous plane of it.
+template <int P, typename T>
+__device__ __forceinline__ void load_cell_column(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase,
+                                                 int le, int ta, int tb) {
+  constexpr int L = P * P, N = P * P * P;
   using Ly = Layout<P>;
+  const T* __restrict__ gc = g + gbase + (le * N + ta + P * tb);
+  T* __restrict__ sc = s + le * Ly::NP + ta + Ly::S1 * tb;
 #pragma unroll
-  for (int k = 0; k < K; ++k) {
-    const int i = threadIdx.x + k * NT;
-    if (i < nvalid * N) {
-      const int le = i / N, l = i - le * N;
-      const int i2 = l / (P * P), i1 = (l / P) % P, i0 = l % P;
-      s[le * Ly::NP + i0 + Ly::S1 * i1 + Ly::S2 * i2] = g[gbase + i];
-    }
-  }
+  for (int j = 0; j < P; ++j) sc[j * Ly::S2] = gc[j * L];
 }
 
 // Volume and face work of one 1D line of one cell in direction DIR, without
@@ -375,10 +371,10 @@ __device__ __forceinline__ void lds_line(const T* __restrict__ sc, int ta, int t
 template <int P, typename T, int DIR>
 __device__ __forceinline__ void global_line(const T* __restrict__ g, uint32_t base, int ta, int tb, T* v) {
   constexpr int L = P * P;
-  const uint32_t off = base + (DIR == 0 ? P * ta + L * tb : (DIR == 1 ? ta + L * tb : ta + P * tb));
+  const T* __restrict__ gl = g + base + (DIR == 0 ? P * ta + L * tb : (DIR == 1 ? ta + L * tb : ta + P * tb));
   constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? P : L);
 #pragma unroll
-  for (int j = 0; j < P; ++j) v[j] = g[off + j * S];
+  for (int j = 0; j < P; ++j) v[j] = gl[j * S];
 }
 
 // Neighbour lines of direction DIR for both sides (x-neighbours inside the
@@ -414,7 +410,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
                    const ScalarArgs<T>* __restrict__ ap) {
   const ScalarArgs<T>& a = *ap;
   constexpr int EB = CellsPerBlock<P>::value;
-  constexpr int L = P * P, N = P * P * P, NT = EB * L;
+  constexpr int L = P * P, N = P * P * P;
   using Ly = Layout<P>;
   __shared__ T sx[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
@@ -435,8 +431,10 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const uint32_t nxy = (uint32_t)nx * ny;
   T nb1[2][P], nk1[2][P], nb2[2][P], nk2[2][P];
   bool has1[2], has2[2];
-  load_cells<P, T, EB, NT>(sx, x, gbase, nvalid);
-  if (KAPPA) load_cells<P, T, EB, NT>(sk, kappa, gbase, nvalid);
+  if (active) {
+    load_cell_column<P, T>(sx, x, gbase, le, ta, tb);
+    if (KAPPA) load_cell_column<P, T>(sk, kappa, gbase, le, ta, tb);
+  }
   __syncthreads();
 
   const T wt = a.wl[li];  // tangential weight w_ta w_tb of this thread's lines
@@ -617,7 +615,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
                      T* __restrict__ ATg, T* __restrict__ dkappa, const ScalarArgs<T>* __restrict__ ap) {
   const ScalarArgs<T>& a = *ap;
   constexpr int EB = AdjCellsPerBlock<P>::value;
-  constexpr int L = P * P, N = P * P * P, NT = EB * L;
+  constexpr int L = P * P, N = P * P * P;
   using Ly = Layout<P>;
   __shared__ T sg[EB * Ly::NP];
   __shared__ T su[EB * Ly::NP];
@@ -630,14 +628,16 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   const int nvalid = min(EB, nx - ex0);
   const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
   const uint32_t gbase = (row + ex0) * N;
-  load_cells<P, T, EB, NT>(sg, g, gbase, nvalid);
-  load_cells<P, T, EB, NT>(su, u, gbase, nvalid);
-  if (KAPPA) load_cells<P, T, EB, NT>(sk, kappa, gbase, nvalid);
-  __syncthreads();
   const int le = threadIdx.x / L;
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
+  if (active) {
+    load_cell_column<P, T>(sg, g, gbase, le, ta, tb);
+    load_cell_column<P, T>(su, u, gbase, le, ta, tb);
+    if (KAPPA) load_cell_column<P, T>(sk, kappa, gbase, le, ta, tb);
+  }
+  __syncthreads();
   const T wt = a.wl[li];
   const int ex = ex0 + le;
   const uint32_t e = row + ex;
