@@ -11,33 +11,38 @@
 // times the line's tangential quadrature weight w_a w_b. K holds the volume
 // term D^T diag(|J|/h_d^2 w) D (for d = 0 also the mass term c |J| diag(w))
 // and the own-cell face terms, L and R the terms coupling to the neighbour
-// (built on the host in long double, one K per pair of side types).
+// (built on the host in long double, one K per pair of side types). The
+// tangential weight times w_i is the node's tensor weight, so the host
+// divides row i of each operator by w_i and the kernel multiplies the sum
+// over the three directions by the tensor weight once per node.
 //
 // Design.
-//  * One wavefront per cell and direction step: the cell's 64 values sit one
-//    per lane in a "line layout" lane = line + 16 node (the 16 lines along d,
-//    node index along d). v_mfma_f64_4x4x4f64 (four 4x4 blocks) multiplies
-//    a 4x4 matrix held one entry per lane into all 16 lines at once, and its
-//    result comes out in the same layout, so the three products of a
-//    direction chain through the accumulator. The matrices cost one VGPR
-//    pair each.
-//  * Each wavefront owns NC consecutive cells of an x-row and issues all of
-//    its global reads first: its cells once in natural node order (the z
-//    layout), the x-lines of the cells beyond both ends, and the y- and
-//    z-neighbour cells read directly in the layout they are used in (the
-//    y-layout read is a permutation inside each 512-byte cell). The x and y
-//    layouts of its own cells are formed with ds_bpermute (no LDS memory),
-//    and the x-neighbours of the inner cells are these same values. The
-//    wavefronts are independent: no barriers, no LDS allocation.
-//  * Per lane, the A-operand entries of the nine interior-cell operators and
-//    the line weight form one 80-byte record (five 16-byte reads); boundary
-//    cells read their own K variant.
-//  * The results of the x and y directions are brought to the natural node
-//    order with ds_bpermute and summed with the z result; one coalesced
-//    store per cell.
+//  * The L2-to-register path issues one load instruction per 64 lanes at a
+//    fixed cost, whatever the width, so cells are read two at a time with
+//    16-byte loads. A "pair layout" holds two x-consecutive cells in one
+//    double2 register: lane = h + 2 t + 8 c + 16 n, components the nodes
+//    i0 = 2h and 2h + 1 of cell c; (t, n) = (i1, i2) for the z direction,
+//    (i2, i1) for the y direction. v_mfma_f64_4x4x4f64 (four 4x4 blocks)
+//    contracts over lane bits 4-5 and keeps bits 0-3 as 16 independent
+//    lines, so each component of a pair register is a valid operand: the
+//    lines of both cells go through one product.
+//  * The x direction needs i0 in lane bits 4-5, one cell per register
+//    ("x layout": lane = i1 + 4 i2 + 16 i0). The own cells are staged in LDS
+//    in natural order and read back in the x and y layouts; the x-lines of
+//    the cells beyond both ends of the chunk are read from global memory.
+//  * Each wavefront owns NC = 4 x-consecutive cells and issues all of its
+//    global reads first: the own cells and the z- and y-neighbour cells in
+//    pairs, the two x-end lines, and its operator record. The A-operand
+//    entries of the nine interior-cell operators and the two nodes' tensor
+//    weights form one 96-byte record per lane; boundary cells read their
+//    own K variant. Wavefronts are independent (one per block).
+//  * Results: the x results are written to LDS in natural order, the y
+//    results added to them in the y-pair layout, and the z results added on
+//    reading them back in the z-pair layout; the sum times the tensor
+//    weight is stored with 16-byte stores.
 //  * Wavefronts walk the sweep order (slab of z-planes, y, z, x-chunk) with
 //    an XCD-aware renumbering (table built on the host), so that the y- and
-//    z-neighbour lines are served by the XCD's L2.
+//    z-neighbour cells are served by the XCD's L2.
 #include <algorithm>
 #include <vector>
 
@@ -46,30 +51,49 @@
 namespace dgi {
 namespace {
 
-constexpr int NC = 4;            // cells per wavefront (consecutive along x)
+constexpr int NC = 4;            // cells per wavefront (consecutive along x): two pairs
 constexpr int T_INT = 0, T_DIR = 1, T_NONE = 2;
 
 __device__ __forceinline__ double mfma(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// value of lane `src` (all lanes take part)
-__device__ __forceinline__ double lane_read(double v, int src) {
-  const int2 w = __builtin_bit_cast(int2, v);
-  int2 r;
-  r.x = __builtin_amdgcn_ds_bpermute(src << 2, w.x);
-  r.y = __builtin_amdgcn_ds_bpermute(src << 2, w.y);
-  return __builtin_bit_cast(double, r);
+// 16-byte load of two doubles (zeros when !v); a native vector type keeps it
+// one dwordx4 load
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 load2(const double* p, bool v) {
+  dvec2 r = {0.0, 0.0};
+  if (v) r = *reinterpret_cast<const dvec2*>(p);
+  return make_double2(r.x, r.y);
 }
 
 __device__ __forceinline__ int side_type(bool has, bool dirichlet) {
   return has ? T_INT : (dirichlet ? T_DIR : T_NONE);
 }
 
+// one direction on a pair register: K u + L u_left + R u_right per component
+__device__ __forceinline__ double2 pair_line(double K, double L, double R, double2 u, double2 ul, double2 ur,
+                                             bool h0, bool h1) {
+  double2 c;
+  c.x = mfma(K, u.x, 0.0);
+  c.y = mfma(K, u.y, 0.0);
+  if (h0) {
+    c.x = mfma(L, ul.x, c.x);
+    c.y = mfma(L, ul.y, c.y);
+  }
+  if (h1) {
+    c.x = mfma(R, ur.x, c.x);
+    c.y = mfma(R, ur.y, c.y);
+  }
+  return c;
+}
+
 // One wavefront per block; the wavefronts are independent.
 __global__ void __launch_bounds__(64)
     k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
                     const uint32_t* __restrict__ waves) {
+  __shared__ __attribute__((aligned(16))) double su[NC * 64];  // own cells, natural node order
+  __shared__ __attribute__((aligned(16))) double sr[NC * 64];  // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
   const int lane = threadIdx.x;
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
@@ -78,49 +102,62 @@ __global__ void __launch_bounds__(64)
   const int nvalid = min(NC, nx - ex0);
   if (nvalid <= 0) return;
 
-  const uint32_t row = (uint32_t)nx * ((uint32_t)ey + (uint32_t)ny * ez);
-  const uint32_t nxy = (uint32_t)nx * ny;
-  const uint32_t c0 = row + ex0;
+  const size_t c0 = (size_t)nx * ((size_t)ey + (size_t)ny * ez) + ex0;
+  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in doubles
   const bool hy0 = ey > 0, hy1 = ey < ny - 1, hz0 = ez > 0, hz1 = ez < nz - 1;
   const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
+  const double* __restrict__ xc = x + c0 * 64;
 
-  double2 rec[5];
+  // pair layouts: lane = h + 2 t + 8 c + 16 n; node offsets of the lane's first node
+  const int h = lane & 1, t = (lane >> 1) & 3, pc = (lane >> 3) & 1, n = lane >> 4;
+  const int offz = 2 * h + 4 * t + 16 * n + 64 * pc;  // node (2h, t, n) of cell pc
+  const int offy = 2 * h + 16 * t + 4 * n + 64 * pc;  // node (2h, n, t) of cell pc
+  // x layout: lane = i1 + 4 i2 + 16 i0
+  const int offx = (lane >> 4) + 4 * (lane & 3) + 16 * ((lane >> 2) & 3);
+
+  double2 uz[2], zl[2], zr[2], yl[2], yr[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const bool v = 2 * p + pc < nvalid;
+    const double* b = xc + 128 * p;
+    uz[p] = load2(b + offz, v);
+    zl[p] = load2(b - sz + offz, v && hz0);
+    zr[p] = load2(b + sz + offz, v && hz1);
+    yl[p] = load2(b - sy + offy, v && hy0);
+    yr[p] = load2(b + sy + offy, v && hy1);
+  }
+  const double xl = hxl ? xc[offx - 64] : 0.0;
+  const double xr = hxr ? xc[64 * nvalid + offx] : 0.0;
+  double2 rec[6];
   const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
 #pragma unroll
-  for (int k = 0; k < 5; ++k) rec[k] = lr[k];
-  // line layouts: lane = l + 16 q, node q along the direction, line l = t1 + 4 t2
-  const int q = lane >> 4, l = lane & 15, t1 = l & 3, t2 = l >> 2;
-  const int nxl = q + 4 * t1 + 16 * t2;  // natural index of the x-layout lane
-  const int nyl = t1 + 4 * q + 16 * t2;  // y-layout (the z-layout is the natural order)
-  const int i0 = lane & 3, i1 = (lane >> 2) & 3, i2 = lane >> 4;
-  const int srcx = i1 + 4 * i2 + 16 * i0, srcy = i0 + 4 * i2 + 16 * i1;  // lanes holding node `lane`
-  const size_t b0 = (size_t)c0 * 64;
-  // global reads: own cells (natural order), x-ends (x layout), y-neighbours (y layout), z-neighbours
-  double uz[NC], xl, xr, uyl[NC], uyr[NC], uzl[NC], uzr[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) uz[k] = k < nvalid ? x[b0 + 64 * k + lane] : 0.0;
-  xl = hxl ? x[b0 - 64 + nxl] : 0.0;
-  xr = hxr ? x[b0 + 64 * nvalid + nxl] : 0.0;
-#pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    uyl[k] = (k < nvalid && hy0) ? x[b0 - (size_t)nx * 64 + 64 * k + nyl] : 0.0;
-    uyr[k] = (k < nvalid && hy1) ? x[b0 + (size_t)nx * 64 + 64 * k + nyl] : 0.0;
-    uzl[k] = (k < nvalid && hz0) ? x[b0 - (size_t)nxy * 64 + 64 * k + lane] : 0.0;
-    uzr[k] = (k < nvalid && hz1) ? x[b0 + (size_t)nxy * 64 + 64 * k + lane] : 0.0;
-  }
+  for (int k = 0; k < 6; ++k) rec[k] = lr[k];
+
   const int ai = 4 * (lane & 3) + (lane >> 4);  // A operand: entry (lane % 4, lane / 16)
   const uint32_t mask = a.mask;
   const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
-  double Kx_int = rec[0].x, Lx = rec[0].y, Rx = rec[1].x, Ky = rec[1].y, Ly = rec[2].x, Ry = rec[2].y;
-  double Kz = rec[3].x, Lz = rec[3].y, Rz = rec[4].x;
-  const double wt = rec[4].y;
+  const double Kx_int = rec[0].x, Lx = rec[0].y, Rx = rec[1].x;
+  double Ky = rec[1].y;
+  const double Ly = rec[2].x, Ry = rec[2].y;
+  double Kz = rec[3].x;
+  const double Lz = rec[3].y, Rz = rec[4].x;
+  const double2 wn = rec[5];
   if (vy != 0) Ky = a.Km[1][vy][ai];
   if (vz != 0) Kz = a.Km[2][vz][ai];
-  // own cells in the x layout (the x-neighbours of the inner cells)
+
+  // own cells to LDS (invalid cells as zeros), back in the x and y layouts
+#pragma unroll
+  for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(su + 128 * p + offz) = uz[p];
+  __syncthreads();
   double ux[NC];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) ux[k] = lane_read(uz[k], nxl);
+  for (int k = 0; k < NC; ++k) ux[k] = su[64 * k + offx];
+  double2 uy[2];
+#pragma unroll
+  for (int p = 0; p < 2; ++p) uy[p] = *reinterpret_cast<const double2*>(su + 128 * p + offy);
+
+  // x direction, one cell per product
 #pragma unroll
   for (int k = 0; k < NC; ++k) {
     if (k < nvalid) {
@@ -133,13 +170,29 @@ __global__ void __launch_bounds__(64)
       double cx = mfma(Kx, ux[k], 0.0);
       if (hx0) cx = mfma(Lx, ul, cx);
       if (hx1) cx = mfma(Rx, ur, cx);
-      double cy = mfma(Ky, lane_read(uz[k], nyl), 0.0);
-      if (hy0) cy = mfma(Ly, uyl[k], cy);
-      if (hy1) cy = mfma(Ry, uyr[k], cy);
-      double cz = mfma(Kz, uz[k], 0.0);
-      if (hz0) cz = mfma(Lz, uzl[k], cz);
-      if (hz1) cz = mfma(Rz, uzr[k], cz);
-      y[b0 + 64 * k + lane] = lane_read(wt * cx, srcx) + lane_read(wt * cy, srcy) + wt * cz;
+      sr[64 * k + offx] = cx;
+    }
+  }
+  __syncthreads();
+  // y direction on pairs, added onto the x results
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (2 * p < nvalid) {
+      const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl[p], yr[p], hy0, hy1);
+      double2* r = reinterpret_cast<double2*>(sr + 128 * p + offy);
+      const double2 o = *r;
+      *r = make_double2(o.x + c.x, o.y + c.y);
+    }
+  }
+  __syncthreads();
+  // z direction on pairs, the sum, the tensor weight, the store
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    if (2 * p < nvalid) {
+      const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl[p], zr[p], hz0, hz1);
+      const double2 o = *reinterpret_cast<const double2*>(sr + 128 * p + offz);
+      if (2 * p + pc < nvalid)
+        *reinterpret_cast<double2*>(y + c0 * 64 + 128 * p + offz) = make_double2(wn.x * (o.x + c.x), wn.y * (o.y + c.y));
     }
   }
 }

@@ -297,27 +297,41 @@ void dgi::derive_face_constants(ScalarArgs<T>& a) {
         const ld two = t == 1 ? 2 : 1;
         return two * fA * e[s][i] * nrm[s][j] + fG * e[s][i] * e[s][j] + two * fB[s] * de[s][i] * e[s][j];
       };
+      // rows divided by the weight of the output node along d: the line's
+      // tangential weight times row i is the full tensor weight of node i
+      // divided by w_i, so the kernel applies one tensor weight per node
+      // after summing the three directions
+      ld winv[4];
+      for (int i = 0; i < 4; ++i) winv[i] = 1 / (ld)(double)a.w[i];
       for (int t0 = 0; t0 < 3; ++t0)
         for (int t1 = 0; t1 < 3; ++t1)
           for (int i = 0; i < 4; ++i)
             for (int j = 0; j < 4; ++j)
-              a.Km[d][3 * t0 + t1][4 * i + j] = (T)(Kvol[i][j] + face(0, t0, i, j) + face(1, t1, i, j));
+              a.Km[d][3 * t0 + t1][4 * i + j] =
+                  (T)(winv[i] * (Kvol[i][j] + face(0, t0, i, j) + face(1, t1, i, j)));
       for (int i = 0; i < 4; ++i)
         for (int j = 0; j < 4; ++j) {
           // neighbour across side 0 meets it with its side 1, across side 1 with its side 0
-          a.Lm[d][4 * i + j] = (T)(-fA * e[0][i] * nrm[1][j] - fG * e[0][i] * e[1][j] - fB[0] * de[0][i] * e[1][j]);
-          a.Rm[d][4 * i + j] = (T)(-fA * e[1][i] * nrm[0][j] - fG * e[1][i] * e[0][j] - fB[1] * de[1][i] * e[0][j]);
+          a.Lm[d][4 * i + j] =
+              (T)(winv[i] * (-fA * e[0][i] * nrm[1][j] - fG * e[0][i] * e[1][j] - fB[0] * de[0][i] * e[1][j]));
+          a.Rm[d][4 * i + j] =
+              (T)(winv[i] * (-fA * e[1][i] * nrm[0][j] - fG * e[1][i] * e[0][j] - fB[1] * de[1][i] * e[0][j]));
         }
     }
     for (int lane = 0; lane < 64; ++lane) {
       const int ai = 4 * (lane & 3) + (lane >> 4);
-      const int t1 = lane & 3, t2 = (lane >> 2) & 3;
       for (int d = 0; d < 3; ++d) {
         a.lrec[lane][3 * d] = (double)a.Km[d][0][ai];
         a.lrec[lane][3 * d + 1] = (double)a.Lm[d][ai];
         a.lrec[lane][3 * d + 2] = (double)a.Rm[d][ai];
       }
-      a.lrec[lane][9] = (double)a.w[t1] * (double)a.w[t2];
+      a.lrec[lane][9] = 0.0;
+      // tensor weights of the two nodes (2h, i1, i2), (2h + 1, i1, i2) the lane
+      // holds in the pair layout lane = h + 2 i1 + 8 cell + 16 i2
+      const int h = lane & 1, i1 = (lane >> 1) & 3, i2 = lane >> 4;
+      const ld wt = (ld)(double)a.w[i1] * (ld)(double)a.w[i2];
+      a.lrec[lane][10] = (double)(wt * (ld)(double)a.w[2 * h]);
+      a.lrec[lane][11] = (double)(wt * (ld)(double)a.w[2 * h + 1]);
     }
   }
 }

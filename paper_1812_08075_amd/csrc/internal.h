@@ -101,20 +101,22 @@ struct alignas(16) ScalarArgs {
   T fG[3];               // |F_d| gamma_d
   T fB[3][2];            // |F_d| c_sym / 2 (2s-1)/h_d
   T wl[PMAX * PMAX];     // w_a w_b: tangential weight of the line a + p b
-  // 1D line operators for kappa = 1 (the matrix-core apply, p = 4): along a
-  // line of direction d, out = K u + L u_left + R u_right before the line's
-  // tangential weight, where K holds the volume term (and the mass term for
-  // d = 0) and the own-cell face terms, L and R the neighbour face terms.
+  LineOp<T> lo[3];     // per direction, kappa = 1
+  // 1D line operators for kappa = 1 of the matrix-core apply (p = 4): along a
+  // line of direction d, out = K u + L u_left + R u_right, where K holds the
+  // volume term (and the mass term for d = 0) and the own-cell face terms,
+  // L and R the neighbour face terms; row i is divided by w_i, so that the
+  // sum over directions times the node's tensor weight is the result.
   // K has one variant per pair of side types (interior, Dirichlet, none):
   // index 3 t0 + t1. Row-major 4 x 4.
-  LineOp<T> lo[3];     // per direction, kappa = 1
   T Km[3][9][16];
   T Lm[3][16];
   T Rm[3][16];
   // per lane of the matrix-core apply: the A operands of the interior cell
-  // (Kx, Lx, Rx, Ky, Ly, Ry, Kz, Lz, Rz, entry (lane % 4, lane / 16)) and the
-  // tangential weight of the lane's line, one 80-byte record per lane
-  double lrec[64][10];
+  // (Kx, Lx, Rx, Ky, Ly, Ry, Kz, Lz, Rz, entry (lane % 4, lane / 16)), a
+  // zero, and the tensor weights of the two nodes the lane holds in the pair
+  // layout: one 96-byte record per lane
+  double lrec[64][12];
   int32_t p;           // nodes per direction
   // geometry in FP64 for the host-side table builders
   double hd[3], detJd, cd, gamd[3];
