@@ -28,21 +28,28 @@
 //    lines of both cells go through one product.
 //  * The x direction needs i0 in lane bits 4-5, one cell per register
 //    ("x layout": lane = i1 + 4 i2 + 16 i0). The own cells are staged in LDS
-//    in natural order and read back in the x and y layouts; the x-lines of
-//    the cells beyond both ends of the chunk are read from global memory.
-//  * Each wavefront owns NC = 4 x-consecutive cells and issues all of its
-//    global reads first: the own cells and the z- and y-neighbour cells in
-//    pairs, the two x-end lines, and its operator record. The A-operand
+//    and read back in the x and y layouts; the x-lines of the cells beyond
+//    both ends of the chunk are read from global memory. The LDS layout is
+//    padded (i1, i2 and cell strides 4, 18, 70 doubles) against bank
+//    conflicts of the three access layouts.
+//  * A wavefront owns NH = 2 steps of NC = 4 x-consecutive cells. Per step
+//    it issues all of its global reads first: the own cells and the z- and
+//    y-neighbour cells in pairs, and the two x-end lines. The A-operand
 //    entries of the nine interior-cell operators and the two nodes' tensor
-//    weights form one 96-byte record per lane; boundary cells read their
-//    own K variant. Wavefronts are independent (one per block).
-//  * Results: the x results are written to LDS in natural order, the y
-//    results added to them in the y-pair layout, and the z results added on
-//    reading them back in the z-pair layout; the sum times the tensor
-//    weight is stored with 16-byte stores.
-//  * Wavefronts walk the sweep order (slab of z-planes, y, z, x-chunk) with
-//    an XCD-aware renumbering (table built on the host), so that the y- and
-//    z-neighbour cells are served by the XCD's L2.
+//    weights form one 96-byte record per lane, read once per wavefront;
+//    boundary cells read their own K variant. Wavefronts are independent
+//    (one per block).
+//  * Results: the x results are written to LDS, the y results added to them
+//    in the y-pair layout, and the z results added on reading them back in
+//    the z-pair layout; the sum times the tensor weight is stored with
+//    16-byte non-temporal stores, which keep the output from displacing
+//    input cells that neighbours still need from L2.
+//  * Each XCD (its own L2) sweeps one region of the mesh: x and z are split
+//    so that the fewest cells are read across region boundaries, y is not
+//    split, and inside a region the wavefronts run y-outermost, then z,
+//    then x, so that the y- and z-neighbour cells are still in the XCD's L2.
+//    The hardware dispatches block b to XCD b mod 8; a table built on the
+//    host maps blocks to wavefront positions accordingly.
 #include <algorithm>
 #include <vector>
 
@@ -51,7 +58,11 @@
 namespace dgi {
 namespace {
 
-constexpr int NC = 4;            // cells per wavefront (consecutive along x): two pairs
+constexpr int NC = 4;            // cells per step (consecutive along x): two pairs
+constexpr int NH = 2;            // steps per wavefront
+// LDS node (i0, i1, i2) of cell c at c LCS + i2 LPS + i1 LIS + i0 (doubles):
+// padded against bank conflicts of the three access layouts
+constexpr int LIS = 4, LPS = 18, LCS = 70;
 constexpr int T_INT = 0, T_DIR = 1, T_NONE = 2;
 
 __device__ __forceinline__ double mfma(double a, double b, double c) {
@@ -88,25 +99,23 @@ __device__ __forceinline__ double2 pair_line(double K, double L, double R, doubl
   return c;
 }
 
-// One wavefront per block; the wavefronts are independent.
+// One wavefront per block; the wavefronts are independent. A wavefront
+// handles NH chunks of NC cells along x, one after the other.
 __global__ void __launch_bounds__(64)
     k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
                     const uint32_t* __restrict__ waves) {
-  __shared__ __attribute__((aligned(16))) double su[NC * 64];  // own cells, natural node order
-  __shared__ __attribute__((aligned(16))) double sr[NC * 64];  // x results, then x + y results
+  __shared__ __attribute__((aligned(16))) double su[NC * LCS];  // own cells
+  __shared__ __attribute__((aligned(16))) double sr[NC * LCS];  // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
   const int lane = threadIdx.x;
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
-  const int ex0 = (int)(w0 & 0xffffu), ey = (int)(w0 >> 16), ez = (int)w1;
+  const int ex00 = (int)(w0 & 0xffffu), ey = (int)(w0 >> 16), ez = (int)w1;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const int nvalid = min(NC, nx - ex0);
-  if (nvalid <= 0) return;
+  if (ex00 >= nx) return;
 
-  const size_t c0 = (size_t)nx * ((size_t)ey + (size_t)ny * ez) + ex0;
+  const size_t row = (size_t)nx * ((size_t)ey + (size_t)ny * ez);
   const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in doubles
   const bool hy0 = ey > 0, hy1 = ey < ny - 1, hz0 = ez > 0, hz1 = ez < nz - 1;
-  const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
-  const double* __restrict__ xc = x + c0 * 64;
 
   // pair layouts: lane = h + 2 t + 8 c + 16 n; node offsets of the lane's first node
   const int h = lane & 1, t = (lane >> 1) & 3, pc = (lane >> 3) & 1, n = lane >> 4;
@@ -114,25 +123,14 @@ __global__ void __launch_bounds__(64)
   const int offy = 2 * h + 16 * t + 4 * n + 64 * pc;  // node (2h, n, t) of cell pc
   // x layout: lane = i1 + 4 i2 + 16 i0
   const int offx = (lane >> 4) + 4 * (lane & 3) + 16 * ((lane >> 2) & 3);
+  const int lz = 2 * h + LIS * t + LPS * n + LCS * pc;  // LDS offsets of the same nodes
+  const int ly = 2 * h + LPS * t + LIS * n + LCS * pc;
+  const int lx = (lane >> 4) + LIS * (lane & 3) + LPS * ((lane >> 2) & 3);
 
-  double2 uz[2], zl[2], zr[2], yl[2], yr[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    const bool v = 2 * p + pc < nvalid;
-    const double* b = xc + 128 * p;
-    uz[p] = load2(b + offz, v);
-    zl[p] = load2(b - sz + offz, v && hz0);
-    zr[p] = load2(b + sz + offz, v && hz1);
-    yl[p] = load2(b - sy + offy, v && hy0);
-    yr[p] = load2(b + sy + offy, v && hy1);
-  }
-  const double xl = hxl ? xc[offx - 64] : 0.0;
-  const double xr = hxr ? xc[64 * nvalid + offx] : 0.0;
   double2 rec[6];
   const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
 #pragma unroll
   for (int k = 0; k < 6; ++k) rec[k] = lr[k];
-
   const int ai = 4 * (lane & 3) + (lane >> 4);  // A operand: entry (lane % 4, lane / 16)
   const uint32_t mask = a.mask;
   const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
@@ -146,53 +144,78 @@ __global__ void __launch_bounds__(64)
   if (vy != 0) Ky = a.Km[1][vy][ai];
   if (vz != 0) Kz = a.Km[2][vz][ai];
 
-  // own cells to LDS (invalid cells as zeros), back in the x and y layouts
-#pragma unroll
-  for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(su + 128 * p + offz) = uz[p];
-  __syncthreads();
-  double ux[NC];
-#pragma unroll
-  for (int k = 0; k < NC; ++k) ux[k] = su[64 * k + offx];
-  double2 uy[2];
-#pragma unroll
-  for (int p = 0; p < 2; ++p) uy[p] = *reinterpret_cast<const double2*>(su + 128 * p + offy);
+  for (int hh = 0; hh < NH; ++hh) {
+    const int ex0 = ex00 + NC * hh;
+    const int nvalid = min(NC, nx - ex0);
+    if (nvalid <= 0) break;
+    const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
+    const double* __restrict__ xc = x + (row + ex0) * 64;
 
-  // x direction, one cell per product
+    double2 uz[2], zl[2], zr[2], yl[2], yr[2];
 #pragma unroll
-  for (int k = 0; k < NC; ++k) {
-    if (k < nvalid) {
-      const int ex = ex0 + k;
-      const bool hx0 = ex > 0, hx1 = ex < nx - 1;
-      const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
-      const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
-      double Kx = Kx_int;
-      if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
-      double cx = mfma(Kx, ux[k], 0.0);
-      if (hx0) cx = mfma(Lx, ul, cx);
-      if (hx1) cx = mfma(Rx, ur, cx);
-      sr[64 * k + offx] = cx;
+    for (int p = 0; p < 2; ++p) {
+      const bool v = 2 * p + pc < nvalid;
+      const double* b = xc + 128 * p;
+      uz[p] = load2(b + offz, v);
+      zl[p] = load2(b - sz + offz, v && hz0);
+      zr[p] = load2(b + sz + offz, v && hz1);
+      yl[p] = load2(b - sy + offy, v && hy0);
+      yr[p] = load2(b + sy + offy, v && hy1);
     }
-  }
-  __syncthreads();
-  // y direction on pairs, added onto the x results
+    const double xl = hxl ? xc[offx - 64] : 0.0;
+    const double xr = hxr ? xc[64 * nvalid + offx] : 0.0;
+
+    // own cells to LDS (invalid cells as zeros), back in the x and y layouts
+    if (hh > 0) __syncthreads();
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    if (2 * p < nvalid) {
-      const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl[p], yr[p], hy0, hy1);
-      double2* r = reinterpret_cast<double2*>(sr + 128 * p + offy);
-      const double2 o = *r;
-      *r = make_double2(o.x + c.x, o.y + c.y);
+    for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(su + 2 * LCS * p + lz) = uz[p];
+    __syncthreads();
+    double ux[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) ux[k] = su[LCS * k + lx];
+    double2 uy[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) uy[p] = *reinterpret_cast<const double2*>(su + 2 * LCS * p + ly);
+
+    // x direction, one cell per product
+#pragma unroll
+    for (int k = 0; k < NC; ++k) {
+      if (k < nvalid) {
+        const int ex = ex0 + k;
+        const bool hx0 = ex > 0, hx1 = ex < nx - 1;
+        const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
+        const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
+        double Kx = Kx_int;
+        if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
+        double cx = mfma(Kx, ux[k], 0.0);
+        if (hx0) cx = mfma(Lx, ul, cx);
+        if (hx1) cx = mfma(Rx, ur, cx);
+        sr[LCS * k + lx] = cx;
+      }
     }
-  }
-  __syncthreads();
-  // z direction on pairs, the sum, the tensor weight, the store
+    __syncthreads();
+    // y direction on pairs, added onto the x results
 #pragma unroll
-  for (int p = 0; p < 2; ++p) {
-    if (2 * p < nvalid) {
-      const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl[p], zr[p], hz0, hz1);
-      const double2 o = *reinterpret_cast<const double2*>(sr + 128 * p + offz);
-      if (2 * p + pc < nvalid)
-        *reinterpret_cast<double2*>(y + c0 * 64 + 128 * p + offz) = make_double2(wn.x * (o.x + c.x), wn.y * (o.y + c.y));
+    for (int p = 0; p < 2; ++p) {
+      if (2 * p < nvalid) {
+        const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl[p], yr[p], hy0, hy1);
+        double2* r = reinterpret_cast<double2*>(sr + 2 * LCS * p + ly);
+        const double2 o = *r;
+        *r = make_double2(o.x + c.x, o.y + c.y);
+      }
+    }
+    __syncthreads();
+    // z direction on pairs, the sum, the tensor weight, the store
+    double* __restrict__ yc = y + (row + ex0) * 64;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (2 * p < nvalid) {
+        const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl[p], zr[p], hz0, hz1);
+        const double2 o = *reinterpret_cast<const double2*>(sr + 2 * LCS * p + lz);
+        if (2 * p + pc < nvalid)
+          __builtin_nontemporal_store(dvec2{wn.x * (o.x + c.x), wn.y * (o.y + c.y)},
+                                      reinterpret_cast<dvec2*>(yc + 128 * p + offz));
+      }
     }
   }
 }
@@ -213,23 +236,61 @@ bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa) {
 hipError_t mfma_setup(dg_mesh& M) {
   if (M.p != 4) return hipSuccess;
   const int nx = M.desc.nx, ny = M.desc.ny, nz = M.desc.nz;
-  const int nc = (nx + NC - 1) / NC;
+  constexpr int CW = NC * NH;  // cells per wavefront along x
+  const int nc = (nx + CW - 1) / CW;
   const int64_t W = (int64_t)nc * ny * nz;
   if (W > 0x7fffffff / 2) return hipErrorInvalidValue;
-  const int sz = nz >= 8 ? nz / 8 : 1;
-  const int per_slab = nc * ny * sz;
-  // logical wavefront t = chunk + nc (z in slab + hz y) + per_slab slab;
-  // hardware block b (one wavefront) runs logical wavefront swizzle(b)
+  // One region of the mesh per XCD: the split (rx, ry, rz), rx ry rz = 8, that
+  // reads the fewest cells across region boundaries (each XCD has its own
+  // L2, so a neighbour cell of another region is fetched again).
+  int best[3] = {1, 1, 8};
+  double best_cost = -1;
+  const int ext[3] = {nc, ny, nz};
+  // The y direction is not split: the sweep runs along y, and its front (the
+  // region's x-z cross-section) is the same for every (rx, rz).
+  for (int rx = 1; rx <= 8; rx *= 2)
+    for (int ry = 1; ry == 1; ry *= 2) {
+      const int rz = 8 / (rx * ry);
+      const int r[3] = {rx, ry, rz};
+      bool ok = true;
+      for (int d = 0; d < 3; ++d) ok = ok && r[d] <= ext[d];
+      if (!ok) continue;
+      const double cost = (double)(rx - 1) * ny * nz + (double)(ry - 1) * nx * nz + (double)(rz - 1) * nx * ny;
+      if (best_cost < 0 || cost < best_cost) {
+        best_cost = cost;
+        best[0] = rx;
+        best[1] = ry;
+        best[2] = rz;
+      }
+    }
+  if (best_cost < 0) best[0] = best[1] = best[2] = 1;  // tiny meshes: one region
+  // region bounds (x in whole chunks)
+  auto bound = [](int n, int r, int i) { return (int)(((int64_t)n * i) / r); };
   const int G = (int)W;
+  std::vector<uint32_t> order(2 * (size_t)G, 0);
+  size_t t = 0;
+  for (int gz = 0; gz < best[2]; ++gz)
+    for (int gy = 0; gy < best[1]; ++gy)
+      for (int gx = 0; gx < best[0]; ++gx) {
+        const int c0 = bound(nc, best[0], gx), c1 = bound(nc, best[0], gx + 1);
+        const int y0 = bound(ny, best[1], gy), y1 = bound(ny, best[1], gy + 1);
+        const int z0 = bound(nz, best[2], gz), z1 = bound(nz, best[2], gz + 1);
+        // inside a region: y outermost, then z, then the x chunks
+        for (int yy = y0; yy < y1; ++yy)
+          for (int zz = z0; zz < z1; ++zz)
+            for (int cc = c0; cc < c1; ++cc) {
+              order[2 * t] = (uint32_t)(cc * CW) | ((uint32_t)yy << 16);
+              order[2 * t + 1] = (uint32_t)zz;
+              ++t;
+            }
+      }
+  if (t != (size_t)G) return hipErrorInvalidValue;
+  // hardware block b (one wavefront) runs logical wavefront swizzle(b)
   std::vector<uint32_t> tab(2 * (size_t)G, 0);
   for (int b = 0; b < G; ++b) {
-    const int t = xcd_swizzle_host(b, G);
-    const int slab = t / per_slab, rem = t - slab * per_slab;
-    const int hz = std::min(sz, nz - slab * sz);
-    const int ey = rem / (nc * hz), rem2 = rem - ey * nc * hz;
-    const int ezi = rem2 / nc, chunk = rem2 - ezi * nc;
-    tab[2 * (size_t)b] = (uint32_t)(chunk * NC) | ((uint32_t)ey << 16);
-    tab[2 * (size_t)b + 1] = (uint32_t)(slab * sz + ezi);
+    const int l = xcd_swizzle_host(b, G);
+    tab[2 * (size_t)b] = order[2 * (size_t)l];
+    tab[2 * (size_t)b + 1] = order[2 * (size_t)l + 1];
   }
   hipError_t e = hipMalloc(&M.d_waves, sizeof(uint32_t) * tab.size());
   if (e != hipSuccess) return e;
