@@ -65,6 +65,7 @@ enum { DG_F64 = 0, DG_F32 = 1 };
 enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
 enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
 enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2 };
+enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1 };
 
 /* Mesh and operator description (all fields are read by dg_mesh_create). */
 typedef struct {
@@ -107,6 +108,8 @@ typedef struct {
   int32_t maxit;            /* CG: iterations; IR: total inner iterations */
   int32_t max_outer;        /* IR: refinement steps */
   int32_t check_every;      /* read the residual norm to the host every n iterations */
+  int32_t precond;          /* DG_PRECOND_*: preconditioner of every CG in the solve (FP64 CG
+                               and the FP32 inner CG alike) */
 } dg_solve_params;
 
 typedef struct {
@@ -141,8 +144,21 @@ dg_status dg_apply(const dg_mesh* mesh, int precision, const void* x, void* y,
 dg_status dg_apply_adjoint(const dg_mesh* mesh, int precision, const void* g, const void* u,
                            const void* kappa, void* ATg, void* dkappa, void* stream);
 
-/* Solves A x = b (diffusion-reaction, theta = -1, so A is SPD) by
- * unpreconditioned CG. Convergence is always judged on the true FP64
+/* z = P r, P the block-Jacobi preconditioner: on every cell T, z_T = B_T^-1 r_T
+ * with B_T the diagonal block of A (the cell's volume terms and its own face
+ * terms). On the axis-aligned cells with kappa = 1, B_T is a sum of
+ * Kronecker products of 1D operators and is inverted exactly by fast
+ * diagonalization (the element block-Jacobi / fast diagonalization
+ * preconditioners cited in Section 1): per direction, the generalized
+ * eigenvectors of the 1D operator against the diagonal GL mass, contracted
+ * along the three directions, a pointwise division, and the transposed
+ * contractions. Diffusion-reaction with kappa_mode DG_KAPPA_ONE and
+ * theta = -1 (else DG_ERR_UNSUPPORTED); FP64 or FP32. Asynchronous. */
+dg_status dg_precond_apply(const dg_mesh* mesh, int precision, const void* r, void* z, void* stream);
+
+/* Solves A x = b (diffusion-reaction, theta = -1, so A is SPD) by CG,
+ * unpreconditioned or with the block-Jacobi preconditioner (params->precond,
+ * same requirements as dg_precond_apply). Convergence is always judged on the true FP64
  * residual ||b - A x||_2 <= rtol ||b||_2.
  *  DG_SOLVE_CG_F64: FP64 throughout.
  *  DG_SOLVE_IR_F32: classic iterative refinement: outer residual b - A x in

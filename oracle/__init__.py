@@ -21,7 +21,8 @@ What it computes, and where the paper defines it:
 * The derivative of L = g^T A(kappa) u with respect to a diffusion coefficient
   given per volume quadrature point.
 * Load vectors, plain conjugate gradients and L2 errors for the
-  manufactured-solution checks.
+  manufactured-solution checks; the element block-Jacobi preconditioner
+  (dense solves with each cell's diagonal block) and preconditioned CG.
 
 Every routine here is pinned by the CPU tests (tests/test_oracle_*.py) to
 things other than itself: library quadrature rules, closed forms, symbolic
@@ -36,7 +37,7 @@ from .problem import Problem, problem_from_workload
 from .blocks import BlockMatrix
 from .scalar import ScalarDG
 from .stokes import StokesDG
-from .solve import cg
+from .solve import cg, pcg, block_jacobi
 
 __all__ = [
     "gauss_legendre", "lagrange_eval", "lagrange_deriv", "HexMesh", "Problem",

@@ -25,6 +25,7 @@ DG_F64, DG_F32 = 0, 1
 DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
 DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
 DG_SOLVE_CG_F64, DG_SOLVE_IR_F32, DG_SOLVE_RU_F32 = 0, 1, 2
+DG_PRECOND_NONE, DG_PRECOND_BLOCK_JACOBI = 0, 1
 
 _DTYPE = {DG_F64: torch.float64, DG_F32: torch.float32}
 
@@ -52,7 +53,7 @@ class dg_mesh_info_t(ctypes.Structure):
 
 class dg_solve_params(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32)]
 
 
 class dg_solve_info(ctypes.Structure):
@@ -62,7 +63,8 @@ class dg_solve_info(ctypes.Structure):
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mesh_info", "dg_apply",
-           "dg_apply_adjoint", "dg_solve", "dg_mesh_qpoints", "dg_load_vector", "dg_last_error")
+           "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_mesh_qpoints", "dg_load_vector",
+           "dg_last_error")
 
 
 def _load():
@@ -78,6 +80,7 @@ def _load():
         "dg_mesh_info": [V, P(dg_mesh_info_t)],
         "dg_apply": [V, ctypes.c_int, V, V, V, V],
         "dg_apply_adjoint": [V, ctypes.c_int, V, V, V, V, V, V],
+        "dg_precond_apply": [V, ctypes.c_int, V, V, V],
         "dg_solve": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
         "dg_mesh_qpoints": [V, P(ctypes.c_double)],
         "dg_load_vector": [V, ctypes.c_int, V, V, V],
@@ -169,9 +172,13 @@ def dg_apply_adjoint(mesh, precision, g, u, kappa, ATg, dkappa=None, stream=None
                                 _stream(stream)))
 
 
+def dg_precond_apply(mesh, precision, r, z, stream=None):
+    _check(lib.dg_precond_apply(mesh, precision, _ptr(r), _ptr(z), _stream(stream)))
+
+
 def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=100000, max_outer=50,
-             check_every=10, stream=None):
-    params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every)
+             check_every=10, precond=DG_PRECOND_NONE, stream=None):
+    params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every, precond)
     info = dg_solve_info()
     st = _check(lib.dg_solve(mesh, mode, _ptr(b), _ptr(x), _ptr(kappa), ctypes.byref(params),
                              ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))

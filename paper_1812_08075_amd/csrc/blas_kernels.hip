@@ -70,6 +70,30 @@ __global__ void __launch_bounds__(RT) k_finalize(const double* __restrict__ part
       st->nrm2 = s;
       if (!isfinite(s)) st->breakdown = 1;
       break;
+    case OP_RR:
+      st->rr = s;
+      if (!isfinite(s)) st->breakdown = 1;
+      break;
+    case OP_SET_RZ:
+      st->rz = s;
+      if (s < 0.0 || !isfinite(s)) st->breakdown = 1;  // P is SPD: r.z >= 0
+      break;
+    case OP_ALPHA_PC: {
+      st->pq = s;
+      const double alpha = (s > 0.0) ? st->rz / s : 0.0;
+      if (!(s > 0.0) || !isfinite(s) || !(alpha < 1e30)) {
+        st->breakdown = 1;
+        st->alpha = 0.0;
+      } else {
+        st->alpha = alpha;
+      }
+      break;
+    }
+    case OP_BETA_PC:
+      st->beta = (st->rz > 0.0) ? s / st->rz : 0.0;
+      st->rz = s;
+      if (!isfinite(s)) st->breakdown = 1;
+      break;
   }
 }
 
@@ -172,7 +196,7 @@ __global__ void k_state_reset(CgState* st, int from_norm) {
 // Zeroes every field of a freshly allocated state record.
 __global__ void k_state_zero(CgState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st->rr = st->rr0 = st->pq = st->alpha = st->beta = st->nrm2 = 0.0;
+    st->rr = st->rr0 = st->pq = st->alpha = st->beta = st->nrm2 = st->rz = 0.0;
     st->breakdown = 0;
     st->pad = 0;
   }
@@ -196,7 +220,7 @@ hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* p
 }
 
 hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int prec, int64_t n, double* partial,
-                          CgState* st, hipStream_t s) {
+                          CgState* st, int op, hipStream_t s) {
   const unsigned g = grid_for(n);
   if (prec == DG_F64)
     hipLaunchKernelGGL(k_cg_update<double>, dim3(g), dim3(RT), 0, s, (double*)x, (double*)r, (const double*)p,
@@ -204,7 +228,13 @@ hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int pr
   else
     hipLaunchKernelGGL(k_cg_update<float>, dim3(g), dim3(RT), 0, s, (float*)x, (float*)r, (const float*)p,
                        (const float*)q, st, n, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, (int)OP_BETA);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, op);
+  return hipGetLastError();
+}
+
+hipError_t blas_finalize(const double* partial, int64_t nb, CgState* st, int op, hipStream_t s) {
+  if (nb < 1 || nb > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)nb, st, op);
   return hipGetLastError();
 }
 

@@ -85,6 +85,116 @@ double penalty_coef(const dg_mesh_desc& d) {
   return d.penalty_form == 0 ? d.alpha * k * (k + 1) : d.alpha * k * (k + 2);
 }
 
+// Eigen decomposition of a symmetric n x n matrix by cyclic Jacobi rotations
+// (long double): B = Q diag(lam) Q^T, Q orthogonal, columns the eigenvectors.
+void symmetric_eigen(int n, long double B[dgi::PMAX][dgi::PMAX], long double Q[dgi::PMAX][dgi::PMAX],
+                     long double* lam) {
+  using ld = long double;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) Q[i][j] = i == j ? 1 : 0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    ld off = 0;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) off += B[i][j] * B[i][j];
+    if (off < 1e-60L) break;
+    for (int i = 0; i < n; ++i)
+      for (int j = i + 1; j < n; ++j) {
+        if (B[i][j] == 0) continue;
+        // rotation in the (i, j) plane that zeroes B[i][j]
+        const ld tau = (B[j][j] - B[i][i]) / (2 * B[i][j]);
+        const ld t = (tau >= 0 ? 1 : -1) / (std::fabs(tau) + std::sqrt(1 + tau * tau));
+        const ld c = 1 / std::sqrt(1 + t * t), sn = t * c;
+        for (int k = 0; k < n; ++k) {  // B <- B R
+          const ld bi = B[k][i], bj = B[k][j];
+          B[k][i] = c * bi - sn * bj;
+          B[k][j] = sn * bi + c * bj;
+        }
+        for (int k = 0; k < n; ++k) {  // B <- R^T B
+          const ld bi = B[i][k], bj = B[j][k];
+          B[i][k] = c * bi - sn * bj;
+          B[j][k] = sn * bi + c * bj;
+        }
+        for (int k = 0; k < n; ++k) {  // Q <- Q R
+          const ld qi = Q[k][i], qj = Q[k][j];
+          Q[k][i] = c * qi - sn * qj;
+          Q[k][j] = sn * qi + c * qj;
+        }
+      }
+  }
+  for (int i = 0; i < n; ++i) lam[i] = B[i][i];
+}
+
+// Tables of the block-Jacobi preconditioner (see ScalarArgs::fdmV): the
+// unscaled line operator K_d of each direction and side-type variant, built
+// from the FP64 1D tables in long double, and its W-orthonormal eigenbasis.
+// Valid for the symmetric operator (theta = -1) with kappa = 1.
+template <typename T>
+void build_fdm(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
+  using ld = long double;
+  a.fdm_ok = 0;
+  if (M.desc.problem != DG_PROBLEM_DIFFREAC || M.desc.kappa_mode != DG_KAPPA_ONE || M.desc.theta != -1.0) return;
+  const dgi::Tables1D& tb = M.tab;
+  const int p = M.p;
+  const int n[3] = {M.desc.nx, M.desc.ny, M.desc.nz};
+  const ld detJ = (ld)1 / n[0] / n[1] / n[2];
+  const ld coef = penalty_coef(M.desc);
+  bool ok = true;
+  for (int d = 0; d < 3; ++d) {
+    const ld h = (ld)1 / n[d];
+    const ld vs = detJ / (h * h), fs = detJ / h;
+    // face coefficients of the symmetric form (consistency and symmetry terms -1)
+    const ld fA = -fs / 2, fG = fs * coef / h;
+    const ld fB[2] = {fs / 2 / h, -fs / 2 / h};
+    ld Kvol[dgi::PMAX][dgi::PMAX];
+    for (int i = 0; i < p; ++i)
+      for (int j = 0; j < p; ++j) {
+        ld acc = 0;
+        for (int q = 0; q < p; ++q) acc += (ld)tb.D[q][i] * vs * (ld)tb.wq[q] * (ld)tb.D[q][j];
+        if (d == 0 && i == j) acc += (ld)M.desc.c * detJ * (ld)tb.wq[i];
+        Kvol[i][j] = acc;
+      }
+    auto face = [&](int sd, int t, int i, int j) -> ld {
+      if (t == 2) return 0;  // natural side: no terms
+      const ld two = t == 1 ? 2 : 1;
+      const ld sg = sd ? 1 : -1;
+      return two * fA * (ld)tb.e[sd][i] * sg * (ld)tb.de[sd][j] / h + fG * (ld)tb.e[sd][i] * (ld)tb.e[sd][j] +
+             two * fB[sd] * (ld)tb.de[sd][i] * (ld)tb.e[sd][j];
+    };
+    for (int t0 = 0; t0 < 3; ++t0)
+      for (int t1 = 0; t1 < 3; ++t1) {
+        const int v = 3 * t0 + t1;
+        // B = W^-1/2 K W^-1/2, symmetrized against rounding
+        ld B[dgi::PMAX][dgi::PMAX], Q[dgi::PMAX][dgi::PMAX], lam[dgi::PMAX];
+        for (int i = 0; i < p; ++i)
+          for (int j = 0; j < p; ++j) {
+            const ld kij = Kvol[i][j] + face(0, t0, i, j) + face(1, t1, i, j);
+            const ld kji = Kvol[j][i] + face(0, t0, j, i) + face(1, t1, j, i);
+            B[i][j] = (kij + kji) / 2 / std::sqrt((ld)tb.wq[i] * (ld)tb.wq[j]);
+          }
+        symmetric_eigen(p, B, Q, lam);
+        for (int i = 0; i < p; ++i) {
+          for (int j = 0; j < p; ++j) a.fdmV[d][v][i * p + j] = (T)(Q[i][j] / std::sqrt((ld)tb.wq[i]));
+          a.fdmL[d][v][i] = (T)lam[i];
+        }
+      }
+  }
+  // every cell's block must be positive definite: lam_x + lam_y + lam_z > 0
+  // over the variants that occur (first, last and an interior position)
+  ld lmin[3] = {1e300L, 1e300L, 1e300L};
+  const uint32_t mask = M.desc.dirichlet_mask;
+  for (int d = 0; d < 3; ++d) {
+    const int pos[3] = {0, n[d] - 1, n[d] >= 3 ? 1 : 0};
+    for (int k = 0; k < 3; ++k) {
+      const int c = pos[k];
+      const int t0 = c > 0 ? 0 : ((mask >> (2 * d)) & 1u ? 1 : 2);
+      const int t1 = c < n[d] - 1 ? 0 : ((mask >> (2 * d + 1)) & 1u ? 1 : 2);
+      for (int i = 0; i < p; ++i) lmin[d] = std::min(lmin[d], (ld)a.fdmL[d][3 * t0 + t1][i]);
+    }
+  }
+  ok = ok && (lmin[0] + lmin[1] + lmin[2] > 0);
+  a.fdm_ok = ok ? 1 : 0;
+}
+
 template <typename T>
 void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
   const dgi::Tables1D& t = M.tab;
@@ -175,6 +285,7 @@ void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
   a.DEh = (T)((p & 1) ? t.de[0][H] : 0.0);
   a.cwm = (T)((p & 1) ? M.desc.c * detJ * t.wq[H] : 0.0);
   dgi::derive_face_constants(a);
+  build_fdm(M, a);
 }
 
 size_t elem_size(int prec) { return prec == DG_F64 ? sizeof(double) : sizeof(float); }
@@ -499,6 +610,23 @@ dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, cons
     }
     hip_check(dgi::scalar_apply(*M, precision, x, y, kap ? kappa : nullptr, false, as_stream(stream)),
               "apply launch");
+    return DG_OK;
+  });
+}
+
+dg_status dg_precond_apply(const dg_mesh* M, int precision, const void* r, void* z, void* stream) {
+  return guarded([&] {
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    check_prec(precision);
+    const size_t es = elem_size(precision);
+    check_vec(r, "r", es);
+    check_vec(z, "z", es);
+    const size_t nb = (size_t)M->ndofs * es;
+    if (overlap(r, nb, z, nb)) fail(DG_ERR_ARG, "r and z overlap");
+    if (!dgi::block_jacobi_supported(*M))
+      fail(DG_ERR_UNSUPPORTED,
+           "the block-Jacobi preconditioner is built for diffusion-reaction with kappa = 1 and theta = -1");
+    hip_check(dgi::block_jacobi(*M, precision, r, z, nullptr, as_stream(stream)), "preconditioner launch");
     return DG_OK;
   });
 }

@@ -136,6 +136,17 @@ struct alignas(16) ScalarArgs {
   T Ep[HMAX], Em[HMAX], Eh;     // (e0_j +- e0_{p-1-j}) / 2 and e0_H
   T DEp[HMAX], DEm[HMAX], DEh;  // the same of de0
   T cwh[HMAX], cwm;             // c |J| w_i / 2 and c |J| w_H (mass term)
+  // Block-Jacobi preconditioner (kappa = 1, axis-aligned cells, theta = -1).
+  // The diagonal block of a cell is sum_d W x W x K_d (K_d the unscaled line
+  // operator of direction d for the cell's side types, W = diag(w) on the two
+  // other directions), so with the generalized eigenpairs K_d V_d =
+  // W V_d diag(lam_d), V_d^T W V_d = I, its inverse is
+  // (V_z x V_y x V_x) diag(1 / (lam_x + lam_y + lam_z)) (V_z x V_y x V_x)^T.
+  // Per direction and side-type variant 3 t0 + t1: fdmV[i p + j] = component
+  // i of eigenvector j; fdmL[j] = lam_j.
+  T fdmV[3][9][PMAX * PMAX];
+  T fdmL[3][9][PMAX];
+  int32_t fdm_ok;  // the tables are valid for this mesh
 };
 
 // Variants of the parameter block kept per mesh.
@@ -192,6 +203,12 @@ void derive_face_constants(ScalarArgs<T>& a);
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa,
                           void* ATg, void* dkappa, hipStream_t s);
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s);
+// z = B^-1 r for the diagonal cell blocks B (requires the tables' fdm_ok);
+// with `partial` != NULL also one partial sum of r.z per block
+// (block_jacobi_blocks(M) entries, fixed order).
+hipError_t block_jacobi(const dg_mesh& M, int prec, const void* r, void* z, double* partial, hipStream_t s);
+int64_t block_jacobi_blocks(const dg_mesh& M);
+inline bool block_jacobi_supported(const dg_mesh& M) { return M.pd[SP_APPLY].fdm_ok != 0; }
 // Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,
 // line weights) and uploads them to M.d_pd / M.d_pf (allocated by the caller).
 hipError_t scalar_params_upload(dg_mesh& M);

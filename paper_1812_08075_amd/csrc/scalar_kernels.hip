@@ -683,6 +683,152 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block-Jacobi preconditioner: z = B_T^-1 r on every cell T, B_T the diagonal
+// block of the operator, by fast diagonalization (tables in
+// ScalarArgs::fdmV, fdmL): the transposed eigenvector contractions along z,
+// y and x, the division by lam_x + lam_y + lam_z on the x-lines, and the
+// eigenvector contractions back along x, y and z. No neighbour data.
+
+// side-type variant 3 t0 + t1 of a cell at position c of n along direction d
+__device__ __forceinline__ int fdm_variant(int c, int n, uint32_t mask, int d) {
+  const int t0 = c > 0 ? 0 : ((mask >> (2 * d)) & 1u ? 1 : 2);
+  const int t1 = c < n - 1 ? 0 : ((mask >> (2 * d + 1)) & 1u ? 1 : 2);
+  return 3 * t0 + t1;
+}
+
+// o = V^T v
+template <int P, typename T>
+__device__ __forceinline__ void fdm_forward(const T* __restrict__ V, const T* v, T* o) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc = fma(V[j * P + i], v[j], acc);
+    o[i] = acc;
+  }
+}
+
+// o = V t
+template <int P, typename T>
+__device__ __forceinline__ void fdm_backward(const T* __restrict__ V, const T* t, T* o) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc = fma(V[i * P + j], t[j], acc);
+    o[i] = acc;
+  }
+}
+
+template <int P, typename T, int DIR>
+__device__ __forceinline__ void lds_store_line(T* __restrict__ sc, int ta, int tb, const T* v) {
+  using Ly = Layout<P>;
+  const int off = DIR == 0 ? Ly::S1 * ta + Ly::S2 * tb : (DIR == 1 ? ta + Ly::S2 * tb : ta + Ly::S1 * tb);
+  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? Ly::S1 : Ly::S2);
+#pragma unroll
+  for (int j = 0; j < P; ++j) sc[off + j * S] = v[j];
+}
+
+// The x-line part of one cell with the tables (V, lam) of its x variant:
+// forward, divide by lam_x + lam_y + lam_z, backward.
+template <int P, typename T>
+__device__ __forceinline__ void fdm_x(const T* V, const T* lam, T lyz, T* v) {
+  T o[P];
+  fdm_forward<P, T>(V, v, o);
+#pragma unroll
+  for (int j = 0; j < P; ++j) o[j] = o[j] / (lam[j] + lyz);
+  fdm_backward<P, T>(V, o, v);
+}
+
+template <int P, typename T>
+__global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
+    k_block_jacobi(const T* __restrict__ r, T* __restrict__ z, const ScalarArgs<T>* __restrict__ ap,
+                   double* __restrict__ partial) {
+  const ScalarArgs<T>& a = *ap;
+  constexpr int EB = CellsPerBlock<P>::value;
+  constexpr int L = P * P, N = P * P * P, NT = EB * L;
+  using Ly = Layout<P>;
+  __shared__ T s[EB * Ly::NP];
+  __shared__ T sV[3 * L], sL[3 * P];  // x tables: first cell, interior, last cell
+  __shared__ double sh[256];
+
+  const BlockCoord bc = block_coord(a);
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int ex0 = bc.ex0;
+  const int nvalid = min(EB, nx - ex0);
+  const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
+  const int le = threadIdx.x / L;
+  const int li = threadIdx.x - le * L;
+  const bool active = le < nvalid;
+  const int ta = li % P, tb = li / P;
+  const uint32_t mask = a.mask;
+  const int vx = fdm_variant(ex0 + le, nx, mask, 0);
+  // x variants in the block: its first cell's, the interior one, its last cell's
+  // block-uniform (made explicit so that the tables are read with scalar loads)
+  const int vy = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ey, ny, mask, 1));
+  const int vz = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ez, nz, mask, 2));
+  const int vfirst = __builtin_amdgcn_readfirstlane(fdm_variant(ex0, nx, mask, 0));
+  const int vlast = __builtin_amdgcn_readfirstlane(fdm_variant(ex0 + nvalid - 1, nx, mask, 0));
+  T* sc = s + le * Ly::NP;
+  for (int i = threadIdx.x; i < 3 * (L + P); i += NT) {
+    const int k = i / (L + P), e = i - k * (L + P);
+    const int u = k == 0 ? vfirst : (k == 1 ? 0 : vlast);
+    if (e < L) sV[k * L + e] = a.fdmV[0][u][e];
+    else sL[k * P + e - L] = a.fdmL[0][u][e - L];
+  }
+  // the thread's column (ta, tb, 0..P-1) is the z-line it owns first
+  const size_t col = (size_t)(row + ex0 + le) * N + ta + P * tb;
+  T rv[P], v[P], o[P];
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) rv[j] = r[col + (size_t)j * L];
+    fdm_forward<P, T>(a.fdmV[2][vz], rv, o);
+    lds_store_line<P, T, 2>(sc, ta, tb, o);
+  }
+  __syncthreads();
+  if (active) {  // y-lines (i0, i2) = (ta, tb)
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_forward<P, T>(a.fdmV[1][vy], v, o);
+    lds_store_line<P, T, 1>(sc, ta, tb, o);
+  }
+  __syncthreads();
+  if (active) {  // x-lines (i1, i2) = (ta, tb), the cell's x tables from LDS
+    lds_line<P, T, 0>(sc, ta, tb, v);
+    const int slot = vx == vfirst ? 0 : (vx == vlast ? 2 : 1);
+    fdm_x<P, T>(sV + slot * L, sL + slot * P, a.fdmL[1][vy][ta] + a.fdmL[2][vz][tb], v);
+    lds_store_line<P, T, 0>(sc, ta, tb, v);
+  }
+  __syncthreads();
+  if (active) {
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[1][vy], v, o);
+    lds_store_line<P, T, 1>(sc, ta, tb, o);
+  }
+  __syncthreads();
+  double rz = 0.0;
+  if (active) {
+    lds_line<P, T, 2>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[2][vz], v, o);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      z[col + (size_t)j * L] = o[j];
+      rz = fma((double)rv[j], (double)o[j], rz);
+    }
+  }
+  if (partial) {  // r.z of the block, fixed-order tree (NT >= 128)
+    if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
+    sh[threadIdx.x] = rz;
+    __syncthreads();
+#pragma unroll
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+  }
+}
+
 // b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
 template <int P, typename T>
 __global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const ScalarArgs<T>* __restrict__ ap,
@@ -752,6 +898,17 @@ hipError_t launch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* kap
   return hipGetLastError();
 }
 
+template <int P, typename T>
+hipError_t launch_block_jacobi(const dg_mesh& M, const T* r, T* z, double* partial, hipStream_t s) {
+  constexpr int EB = CellsPerBlock<P>::value;
+  static_assert(EB * P * P >= 128 && EB * P * P <= 256, "block reduction assumes 128..256 threads");
+  const int64_t G = grid_of(host_params<T>(M)[SP_APPLY]);
+  if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const ScalarArgs<T>* ap = device_params<T>(M) + SP_APPLY;
+  hipLaunchKernelGGL((k_block_jacobi<P, T>), dim3((unsigned)G), dim3(EB * P * P), 0, s, r, z, ap, partial);
+  return hipGetLastError();
+}
+
 // Cells per block of the apply and adjoint kernels for p nodes per direction.
 int apply_cells_per_block(int p) { return 256 / (p * p) > 0 ? 256 / (p * p) : 1; }
 int adjoint_cells_per_block(int p) { return 128 / (p * p) > 0 ? 128 / (p * p) : 1; }
@@ -779,6 +936,13 @@ template <typename T>
 hipError_t dispatch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* kappa, T* ATg, T* dk,
                             hipStream_t s) {
 #define DG_CALL(PP) launch_adjoint<PP, T>(M, g, u, kappa, ATg, dk, s)
+  DG_DISPATCH_P(M.p, DG_CALL)
+#undef DG_CALL
+}
+
+template <typename T>
+hipError_t dispatch_block_jacobi(const dg_mesh& M, const T* r, T* z, double* partial, hipStream_t s) {
+#define DG_CALL(PP) launch_block_jacobi<PP, T>(M, r, z, partial, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
@@ -862,6 +1026,13 @@ hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void*
   return dispatch_adjoint<float>(M, (const float*)g, (const float*)u, (const float*)kappa, (float*)ATg,
                                  (float*)dkappa, s);
 }
+
+hipError_t block_jacobi(const dg_mesh& M, int prec, const void* r, void* z, double* partial, hipStream_t s) {
+  if (prec == DG_F64) return dispatch_block_jacobi<double>(M, (const double*)r, (double*)z, partial, s);
+  return dispatch_block_jacobi<float>(M, (const float*)r, (float*)z, partial, s);
+}
+
+int64_t block_jacobi_blocks(const dg_mesh& M) { return grid_of(M.pd[SP_APPLY]); }
 
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s) {
   if (prec == DG_F64) return dispatch_load<double>(M, (const double*)fq, (double*)b, s);

@@ -1,6 +1,9 @@
 // Matrix-free solvers of the SIPG system A x = b (diffusion-reaction, theta = -1,
-// so A is symmetric positive definite): unpreconditioned CG in FP64, and two
-// refinement schemes whose CG applies the FP32 operator.
+// so A is symmetric positive definite): CG in FP64, and two refinement
+// schemes whose CG applies the FP32 operator. Every CG runs either
+// unpreconditioned or with the block-Jacobi preconditioner z = P r (the
+// inverse diagonal cell blocks; PCG: alpha = r.z / p.Ap, beta = r_new.z_new /
+// r.z, p = z + beta p; r.z comes out of the preconditioner kernel).
 //
 // Classic refinement (DG_SOLVE_IR_F32): r = b - A x in FP64 (FP64 apply),
 // rhat = r / |r| rounded to FP32, a fresh inner CG on A_32 d = rhat with FP32
@@ -64,8 +67,10 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
 
 class Solver {
  public:
-  Solver(const dg_mesh& M, const void* kappa, hipStream_t s) : M_(M), kappa_(kappa), s_(s), n_(M.ndofs) {
-    dev_alloc(partial_, sizeof(double) * dgi::RED_BLOCKS);
+  Solver(const dg_mesh& M, const void* kappa, bool pc, hipStream_t s)
+      : M_(M), kappa_(kappa), s_(s), n_(M.ndofs), pc_(pc) {
+    const int64_t np = pc ? std::max<int64_t>(dgi::RED_BLOCKS, dgi::block_jacobi_blocks(M)) : dgi::RED_BLOCKS;
+    dev_alloc(partial_, sizeof(double) * np);
     dev_alloc(state_, sizeof(dgi::CgState));
     if (hipHostMalloc(&host_.p, sizeof(dgi::CgState)) != hipSuccess) {
       (void)hipGetLastError();
@@ -87,6 +92,39 @@ class Solver {
     ck(dgi::scalar_apply(M_, prec, x, y, kappa, false, s_), "apply");
   }
 
+  bool preconditioned() const { return pc_; }
+
+  // z = P r and r.z reduced into the state with `op` (OP_SET_RZ or OP_BETA_PC)
+  void precond(int prec, const void* r, void* z, int op) {
+    ck(dgi::block_jacobi(M_, prec, r, z, partial(), s_), "preconditioner");
+    ck(dgi::blas_finalize(partial(), dgi::block_jacobi_blocks(M_), st(), op, s_), "r.z");
+  }
+
+  // first search direction of a (re)started CG: p = P r (with rz) or p = r
+  void start_direction(int prec, const void* r, void* p, void* z) {
+    if (pc_) {
+      precond(prec, r, z, dgi::OP_SET_RZ);
+      ck(dgi::blas_copy(z, p, prec, n_, s_), "p = z");
+    } else {
+      ck(dgi::blas_copy(r, p, prec, n_, s_), "p = r");
+    }
+  }
+
+  // one CG iteration: q = A p, x += alpha p, r -= alpha q, p = r + beta p
+  // (preconditioned: z = P r, p = z + beta p)
+  void iterate(int prec, void* x, void* r, void* p, void* q, void* z, const void* kappa) {
+    apply(prec, p, q, kappa);
+    ck(dgi::blas_dot(p, q, prec, n_, partial(), st(), pc_ ? dgi::OP_ALPHA_PC : dgi::OP_ALPHA, s_), "p.Ap");
+    ck(dgi::blas_cg_update(x, r, p, q, prec, n_, partial(), st(), pc_ ? dgi::OP_RR : dgi::OP_BETA, s_),
+       "cg update");
+    if (pc_) {
+      precond(prec, r, z, dgi::OP_BETA_PC);
+      ck(dgi::blas_xpay(z, p, prec, n_, st(), s_), "p update");
+    } else {
+      ck(dgi::blas_xpay(r, p, prec, n_, st(), s_), "p update");
+    }
+  }
+
   // nrm2 = |b - A x|^2 with r = b - A x (q is scratch)
   double true_residual(const double* b, const double* x, double* r, double* q) {
     apply(DG_F64, x, q, kappa_);
@@ -94,10 +132,11 @@ class Solver {
     return read().nrm2;
   }
 
-  // CG on A_prec z = rhs (r holds the initial residual rhs - A z, p a copy
-  // of it, st()->rr its square norm). Runs until sqrt(rr) <= tol or `budget`
-  // iterations; returns the iterations done.
-  int cg(int prec, void* z, void* r, void* p, void* q, const void* kappa, double tol, int budget, int check,
+  // CG on A_prec z = rhs (r holds the initial residual rhs - A z, p the
+  // first search direction from start_direction, st()->rr the square norm of
+  // r). Runs until sqrt(rr) <= tol or `budget` iterations; returns the
+  // iterations done. zp: preconditioned residual (preconditioned runs).
+  int cg(int prec, void* z, void* r, void* p, void* q, void* zp, const void* kappa, double tol, int budget, int check,
          int* breakdown) {
     int it = 0;
     while (it < budget) {
@@ -109,10 +148,7 @@ class Solver {
         }
         if (std::sqrt(h.rr) <= tol) return it;
       }
-      apply(prec, p, q, kappa);
-      ck(dgi::blas_dot(p, q, prec, n_, partial(), st(), dgi::OP_ALPHA, s_), "p.Ap");
-      ck(dgi::blas_cg_update(z, r, p, q, prec, n_, partial(), st(), s_), "cg update");
-      ck(dgi::blas_xpay(r, p, prec, n_, st(), s_), "p update");
+      iterate(prec, z, r, p, q, zp, kappa);
       ++it;
     }
     const dgi::CgState h = read();
@@ -128,6 +164,7 @@ class Solver {
   const void* kappa_;
   hipStream_t s_;
   int64_t n_;
+  bool pc_;
   DevMem partial_, state_;
   HostPinned host_;
 };
@@ -135,7 +172,8 @@ class Solver {
 dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa, const dg_solve_params* prm,
               dg_solve_info* info, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
-  Solver S(*M, kappa, s);
+  const bool pc = prm->precond == DG_PRECOND_BLOCK_JACOBI;
+  Solver S(*M, kappa, pc, s);
   const int64_t n = S.n();
   const int check = prm->check_every > 0 ? prm->check_every : 10;
   DevMem r, p, q;
@@ -157,14 +195,16 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
   double res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
 
   if (mode == DG_SOLVE_CG_F64) {
+    DevMem zv;
     dev_alloc(p, sizeof(double) * n);
+    if (pc) dev_alloc(zv, sizeof(double) * n);
     int total = 0;
     // restart from the true residual whenever the recursive one has converged but
     // the true one has not (residual replacement)
     while (res > target && total < prm->maxit && !breakdown) {
       ck(dgi::blas_state_from_norm(S.st(), s), "state");
-      ck(dgi::blas_copy(r.p, p.p, DG_F64, n, s), "p = r");
-      total += S.cg(DG_F64, x, r.p, p.p, q.p, kappa, target, prm->maxit - total, check, &breakdown);
+      S.start_direction(DG_F64, r.p, p.p, zv.p);
+      total += S.cg(DG_F64, x, r.p, p.p, q.p, zv.p, kappa, target, prm->maxit - total, check, &breakdown);
       res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
     }
     info->iterations = total;
@@ -174,11 +214,12 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     // replacement; the search direction is kept across replacements
     // below ~1e-3 per correction the FP32 recursion would run past FP32 accuracy
     const double RU_DROP = (prm->inner_rtol >= 1e-3 && prm->inner_rtol < 1.0) ? prm->inner_rtol : 0.1;
-    DevMem rl, pl, ql, xl, k32;
+    DevMem rl, pl, ql, xl, zl, k32;
     dev_alloc(rl, sizeof(float) * n);
     dev_alloc(pl, sizeof(float) * n);
     dev_alloc(ql, sizeof(float) * n);
     dev_alloc(xl, sizeof(float) * n);
+    if (pc) dev_alloc(zl, sizeof(float) * n);
     const void* kap32 = nullptr;
     if (kappa) {
       dev_alloc(k32, sizeof(float) * M->nqp);
@@ -187,7 +228,7 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     }
     ck(dgi::blas_zero(xl.p, DG_F32, n, s), "xl = 0");
     ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
-    ck(dgi::blas_copy(rl.p, pl.p, DG_F32, n, s), "p = r");
+    S.start_direction(DG_F32, rl.p, pl.p, zl.p);
     ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
     double last = std::sqrt(S.read().rr);
     double lowest = last;  // smallest recursive residual since the last correction
@@ -195,12 +236,8 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     int growth = 0;        // consecutive checks with a growing residual
     int total = 0, outer = 0, since_restart = 0;
     while (res > target && total < prm->maxit && !breakdown) {
-      for (int it = 0; it < check && total < prm->maxit; ++it, ++total, ++since_restart) {
-        S.apply(DG_F32, pl.p, ql.p, kap32);
-        ck(dgi::blas_dot(pl.p, ql.p, DG_F32, n, S.partial(), S.st(), dgi::OP_ALPHA, s), "p.Ap");
-        ck(dgi::blas_cg_update(xl.p, rl.p, pl.p, ql.p, DG_F32, n, S.partial(), S.st(), s), "cg update");
-        ck(dgi::blas_xpay(rl.p, pl.p, DG_F32, n, S.st(), s), "p update");
-      }
+      for (int it = 0; it < check && total < prm->maxit; ++it, ++total, ++since_restart)
+        S.iterate(DG_F32, xl.p, rl.p, pl.p, ql.p, zl.p, kap32);
       const dgi::CgState h = S.read();
       const double cur = std::sqrt(h.rr);
       // The FP32 recursion can lose its footing once its residual has drifted
@@ -230,8 +267,11 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
         ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
         if (lost) {
           ck(dgi::blas_state_zero(S.st(), s), "state reset");
-          ck(dgi::blas_copy(rl.p, pl.p, DG_F32, n, s), "p = r");
+          S.start_direction(DG_F32, rl.p, pl.p, zl.p);
           since_restart = 0;
+        } else if (pc) {
+          // the kept direction continues with r.z of the replaced residual
+          S.precond(DG_F32, rl.p, zl.p, dgi::OP_SET_RZ);
         }
         ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
         last = lowest = prev = std::sqrt(S.read().rr);
@@ -241,11 +281,12 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     info->iterations = total;
     info->outer = outer;
   } else {
-    DevMem rh, ph, qh, dh, k32;
+    DevMem rh, ph, qh, dh, zh, k32;
     dev_alloc(rh, sizeof(float) * n);
     dev_alloc(ph, sizeof(float) * n);
     dev_alloc(qh, sizeof(float) * n);
     dev_alloc(dh, sizeof(float) * n);
+    if (pc) dev_alloc(zh, sizeof(float) * n);
     const void* kap32 = nullptr;
     if (kappa) {
       dev_alloc(k32, sizeof(float) * M->nqp);
@@ -257,9 +298,11 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       // S.true_residual left r = b - A x and nrm2 = |r|^2 on the device
       ck(dgi::blas_ir_start((const double*)r.p, (float*)rh.p, (float*)ph.p, (float*)dh.p, n, S.st(), s), "ir start");
       ck(dgi::blas_dot(rh.p, rh.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "rhat.rhat");
+      if (pc) S.start_direction(DG_F32, rh.p, ph.p, zh.p);  // blas_ir_start set p = rhat
       const double inner_tol = prm->inner_rtol * std::sqrt(S.read().rr0);
       int inner_lost = 0;
-      const int its = S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, kap32, inner_tol, prm->maxit - total, check, &inner_lost);
+      const int its =
+          S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, zh.p, kap32, inner_tol, prm->maxit - total, check, &inner_lost);
       total += its;
       // nrm2 still holds |r|^2 of this outer step
       ck(dgi::blas_ir_correct(x, (const float*)dh.p, n, S.st(), s), "x += |r| d");
@@ -307,6 +350,14 @@ extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, doubl
     if (!(prm->rtol > 0) || prm->maxit < 1 || (mode == DG_SOLVE_IR_F32 && (!(prm->inner_rtol > 0) || prm->max_outer < 1))) {
       dg_set_error("rtol, inner_rtol must be > 0; maxit, max_outer >= 1");
       return DG_ERR_ARG;
+    }
+    if (prm->precond != DG_PRECOND_NONE && prm->precond != DG_PRECOND_BLOCK_JACOBI) {
+      dg_set_error("unknown preconditioner");
+      return DG_ERR_ARG;
+    }
+    if (prm->precond == DG_PRECOND_BLOCK_JACOBI && !dgi::block_jacobi_supported(*M)) {
+      dg_set_error("the block-Jacobi preconditioner is built for kappa = 1 and theta = -1");
+      return DG_ERR_UNSUPPORTED;
     }
     const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
     if (kap && !kappa) {

@@ -15,18 +15,35 @@ struct CgState {
   double alpha;
   double beta;
   double nrm2;    // last norm computed with OP_NORM (outer residual of the refinement)
+  double rz;      // r.z, z = P r (preconditioned CG)
   int32_t breakdown;
   int32_t pad;
 };
 
-enum : int { OP_SET_RR = 0, OP_ALPHA = 1, OP_BETA = 2, OP_NORM = 3 };
+// OP_SET_RR: rr = rr0 = s. OP_ALPHA: pq = s, alpha = rr / pq. OP_BETA: beta =
+// s / rr, rr = s. OP_NORM: nrm2 = s. Preconditioned CG: OP_RR: rr = s;
+// OP_SET_RZ: rz = s; OP_ALPHA_PC: pq = s, alpha = rz / pq; OP_BETA_PC:
+// beta = s / rz, rz = s.
+enum : int {
+  OP_SET_RR = 0,
+  OP_ALPHA = 1,
+  OP_BETA = 2,
+  OP_NORM = 3,
+  OP_RR = 4,
+  OP_SET_RZ = 5,
+  OP_ALPHA_PC = 6,
+  OP_BETA_PC = 7
+};
 
 // a.b (FP64 accumulation) reduced into the state with `op`.
 hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* partial, CgState* st, int op,
                     hipStream_t s);
-// x += alpha p, r -= alpha q, then beta = r.r / rr_old, rr = r.r.
+// x += alpha p, r -= alpha q, then the new r.r reduced with `op` (OP_BETA:
+// beta = r.r / rr_old, rr = r.r; OP_RR for preconditioned CG: rr = r.r).
 hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int prec, int64_t n, double* partial,
-                          CgState* st, hipStream_t s);
+                          CgState* st, int op, hipStream_t s);
+// Sums nb partial sums (fixed order) and applies `op` to the state.
+hipError_t blas_finalize(const double* partial, int64_t nb, CgState* st, int op, hipStream_t s);
 hipError_t blas_xpay(const void* r, void* p, int prec, int64_t n, CgState* st, hipStream_t s);
 // r = b - Ax, nrm2 = r.r.
 hipError_t blas_residual(const double* b, const double* Ax, double* r, int64_t n, double* partial, CgState* st,
