@@ -149,9 +149,27 @@ def cpu_baseline(target_s=12.0):
                       f"{reps} applies in {el:.1f} s; host has {os.cpu_count()} logical CPUs"}
 
 
+def bench_precond(dg, w, prec, steps, warmup):
+    """z = P r with the block-Jacobi preconditioner (fast diagonalization):
+    read r, write z, 12 p^4 + p^3 flops per cell."""
+    import torch
+    import workloads
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    dt = torch.float64 if prec == dg.DG_F64 else torch.float32
+    r = torch.from_numpy(workloads.inputs(w, "x")).to("cuda", dt)
+    z = torch.empty_like(r)
+    stream = torch.cuda.current_stream()
+    ms = time_applies(lambda: dg.dg_precond_apply(mesh.handle, prec, r, z, stream), steps, warmup, stream)
+    info = mesh.info
+    p = info.p
+    es = 8 if prec == dg.DG_F64 else 4
+    return rates(info, ms, prec, nbytes=2.0 * es * info.ndofs, flops=info.nelem * (12.0 * p ** 4 + p ** 3))
+
+
 def bench_solve(dg, rtol=1e-10):
-    """Q5 40^3 manufactured sin problem: plain FP64 CG vs FP32-apply iterative
-    refinement, both to the same true relative residual, from x0 = 0."""
+    """Q5 40^3 manufactured sin problem: FP64 CG vs FP32-apply iterative
+    refinement, all to the same true relative residual, from x0 = 0; each
+    unpreconditioned and with the block-Jacobi preconditioner."""
     import torch
     import workloads
     w = workloads.WORKLOADS[5]
@@ -163,23 +181,32 @@ def bench_solve(dg, rtol=1e-10):
     dg.dg_load_vector(mesh.handle, dg.DG_F64, fq, b)
     out = {}
     sol = {}
-    inner = {"cg_f64": 1e-5, "ir_f32": 1e-5, "ru_f32": 0.1}
-    for name, mode in (("cg_f64", dg.DG_SOLVE_CG_F64), ("ir_f32", dg.DG_SOLVE_IR_F32),
-                       ("ru_f32", dg.DG_SOLVE_RU_F32)):
+    # inner tolerance / reliable-update drop per mode, chosen by a sweep at this size
+    inner = {"cg_f64": 1e-5, "ir_f32": 1e-5, "ru_f32": 0.1, "ir_f32_bj": 1e-3}
+    runs = []
+    for pc, suffix in ((dg.DG_PRECOND_NONE, ""), (dg.DG_PRECOND_BLOCK_JACOBI, "_bj")):
+        for base, mode in (("cg_f64", dg.DG_SOLVE_CG_F64), ("ir_f32", dg.DG_SOLVE_IR_F32),
+                           ("ru_f32", dg.DG_SOLVE_RU_F32)):
+            runs.append((base + suffix, base, mode, pc))
+    for name, base, mode, pc in runs:
         log(f"solve {name}")
         x = torch.zeros_like(b)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=rtol, inner_rtol=inner[name], maxit=200000,
-                               max_outer=20, check_every=20)
+        st, info = dg.dg_solve(mesh.handle, mode, b, x, rtol=rtol, inner_rtol=inner.get(name, inner[base]),
+                               maxit=200000, max_outer=20, check_every=10, precond=pc)
         el = time.perf_counter() - t0
         out[name] = {"status": st, "seconds": el, "iterations": info.iterations, "outer": info.outer,
                      "true_rel_residual": info.rel_residual}
         sol[name] = x
-    for name in ("ir_f32", "ru_f32"):
-        out[f"speedup_{name}_over_cg_f64"] = out["cg_f64"]["seconds"] / out[name]["seconds"]
-        d = sol[name] - sol["cg_f64"]
-        out[f"rel_diff_{name}_vs_cg_f64"] = float(torch.linalg.norm(d) / torch.linalg.norm(sol["cg_f64"]))
+    for suffix in ("", "_bj"):
+        ref = "cg_f64" + suffix
+        for base in ("ir_f32", "ru_f32"):
+            name = base + suffix
+            out[f"speedup_{name}_over_{ref}"] = out[ref]["seconds"] / out[name]["seconds"]
+            d = sol[name] - sol["cg_f64"]
+            out[f"rel_diff_{name}_vs_cg_f64"] = float(torch.linalg.norm(d) / torch.linalg.norm(sol["cg_f64"]))
+    out["speedup_cg_f64_bj_over_cg_f64"] = out["cg_f64"]["seconds"] / out["cg_f64_bj"]["seconds"]
     out["workload"] = w.name
     return out
 
@@ -231,6 +258,9 @@ def main():
         if args.only == "q4":
             r = bench_adjoint(dg, w, args.steps, args.warmup)
             log(f"{w.name} adjoint: {r['ms'] * 1e3:.1f} us")
+        if args.only == "q5":
+            r = bench_precond(dg, w, dg.DG_F64, args.steps, args.warmup)
+            log(f"{w.name} block-Jacobi: {r['ms'] * 1e3:.1f} us")
         return
 
     w2 = workloads.WORKLOADS[2]
@@ -272,6 +302,9 @@ def main():
         log("Q4 FP64 adjoint (A^T g and dL/dkappa)")
         extra["adjoint_q4_kappa_f64"] = bench_adjoint(dg, w4, args.steps, args.warmup)
         del m4, m5
+        log("Q5 block-Jacobi preconditioner FP64 / FP32")
+        extra["precond_q5_f64"] = bench_precond(dg, w5, dg.DG_F64, args.steps, args.warmup)
+        extra["precond_q5_f32"] = bench_precond(dg, w5, dg.DG_F32, args.steps, args.warmup)
     if not args.no_solve and not args.no_extra:
         extra["solve_q5_40cube"] = bench_solve(dg)
 
