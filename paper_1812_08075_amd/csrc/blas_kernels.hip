@@ -97,16 +97,15 @@ __global__ void __launch_bounds__(RT) k_finalize(const double* __restrict__ part
   }
 }
 
-// x += alpha p; r -= alpha q; partial sums of r.r
+// r -= alpha q; partial sums of r.r
 template <typename T>
-__global__ void __launch_bounds__(RT) k_cg_update(T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
-                                                  const T* __restrict__ q, const CgState* __restrict__ st,
-                                                  int64_t n, double* __restrict__ partial) {
+__global__ void __launch_bounds__(RT) k_r_update(T* __restrict__ r, const T* __restrict__ q,
+                                                 const CgState* __restrict__ st, int64_t n,
+                                                 double* __restrict__ partial) {
   __shared__ double sh[RT];
   const T a = (T)st->alpha;
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
-    x[i] = fma(a, p[i], x[i]);
     const T ri = fma(-a, q[i], r[i]);
     r[i] = ri;
     acc = fma((double)ri, (double)ri, acc);
@@ -115,13 +114,16 @@ __global__ void __launch_bounds__(RT) k_cg_update(T* __restrict__ x, T* __restri
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// p = r + beta p
+// x += alpha p; p = z + beta p (z: the residual, or the preconditioned one)
 template <typename T>
-__global__ void __launch_bounds__(RT) k_xpay(const T* __restrict__ r, T* __restrict__ p,
-                                             const CgState* __restrict__ st, int64_t n) {
-  const T b = (T)st->beta;
-  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT)
-    p[i] = fma(b, p[i], r[i]);
+__global__ void __launch_bounds__(RT) k_xp_update(T* __restrict__ x, T* __restrict__ p, const T* __restrict__ z,
+                                                  const CgState* __restrict__ st, int64_t n) {
+  const T a = (T)st->alpha, b = (T)st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    const T pi = p[i];
+    x[i] = fma(a, pi, x[i]);
+    p[i] = fma(b, pi, z[i]);
+  }
 }
 
 // r = b - Ax (FP64); partial sums of r.r
@@ -219,31 +221,30 @@ hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* p
   return hipGetLastError();
 }
 
-hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int prec, int64_t n, double* partial,
-                          CgState* st, int op, hipStream_t s) {
-  const unsigned g = grid_for(n);
-  if (prec == DG_F64)
-    hipLaunchKernelGGL(k_cg_update<double>, dim3(g), dim3(RT), 0, s, (double*)x, (double*)r, (const double*)p,
-                       (const double*)q, st, n, partial);
-  else
-    hipLaunchKernelGGL(k_cg_update<float>, dim3(g), dim3(RT), 0, s, (float*)x, (float*)r, (const float*)p,
-                       (const float*)q, st, n, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, op);
-  return hipGetLastError();
-}
-
 hipError_t blas_finalize(const double* partial, int64_t nb, CgState* st, int op, hipStream_t s) {
   if (nb < 1 || nb > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)nb, st, op);
   return hipGetLastError();
 }
 
-hipError_t blas_xpay(const void* r, void* p, int prec, int64_t n, CgState* st, hipStream_t s) {
+hipError_t blas_r_update(void* r, const void* q, int prec, int64_t n, double* partial, CgState* st, int op,
+                         hipStream_t s) {
   const unsigned g = grid_for(n);
   if (prec == DG_F64)
-    hipLaunchKernelGGL(k_xpay<double>, dim3(g), dim3(RT), 0, s, (const double*)r, (double*)p, st, n);
+    hipLaunchKernelGGL(k_r_update<double>, dim3(g), dim3(RT), 0, s, (double*)r, (const double*)q, st, n, partial);
   else
-    hipLaunchKernelGGL(k_xpay<float>, dim3(g), dim3(RT), 0, s, (const float*)r, (float*)p, st, n);
+    hipLaunchKernelGGL(k_r_update<float>, dim3(g), dim3(RT), 0, s, (float*)r, (const float*)q, st, n, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, op);
+  return hipGetLastError();
+}
+
+hipError_t blas_xp_update(void* x, void* p, const void* z, int prec, int64_t n, CgState* st, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  if (prec == DG_F64)
+    hipLaunchKernelGGL(k_xp_update<double>, dim3(g), dim3(RT), 0, s, (double*)x, (double*)p, (const double*)z, st,
+                       n);
+  else
+    hipLaunchKernelGGL(k_xp_update<float>, dim3(g), dim3(RT), 0, s, (float*)x, (float*)p, (const float*)z, st, n);
   return hipGetLastError();
 }
 

@@ -207,6 +207,10 @@ hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipS
 // with `partial` != NULL also one partial sum of r.z per block
 // (block_jacobi_blocks(M) entries, fixed order).
 hipError_t block_jacobi(const dg_mesh& M, int prec, const void* r, void* z, double* partial, hipStream_t s);
+// The same after the residual update r -= alpha q (alpha in device memory),
+// with partial sums of r.z and of the updated r.r (one pass for PCG).
+hipError_t block_jacobi_update(const dg_mesh& M, int prec, void* r, const void* q, const double* alpha, void* z,
+                               double* partial_rz, double* partial_rr, hipStream_t s);
 int64_t block_jacobi_blocks(const dg_mesh& M);
 inline bool block_jacobi_supported(const dg_mesh& M) { return M.pd[SP_APPLY].fdm_ok != 0; }
 // Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,

@@ -741,10 +741,14 @@ __device__ __forceinline__ void fdm_x(const T* V, const T* lam, T lyz, T* v) {
   fdm_backward<P, T>(V, o, v);
 }
 
+// With q != NULL the residual is first updated in place, r -= alpha q (alpha
+// read from device memory), and partial sums of r.r go to partial_rr: one
+// pass over r, q and z per conjugate-gradient iteration.
 template <int P, typename T>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
-    k_block_jacobi(const T* __restrict__ r, T* __restrict__ z, const ScalarArgs<T>* __restrict__ ap,
-                   double* __restrict__ partial) {
+    k_block_jacobi(T* __restrict__ r, T* __restrict__ z, const ScalarArgs<T>* __restrict__ ap,
+                   double* __restrict__ partial, const T* __restrict__ q, const double* __restrict__ alpha,
+                   double* __restrict__ partial_rr) {
   const ScalarArgs<T>& a = *ap;
   constexpr int EB = CellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
@@ -780,9 +784,20 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   // the thread's column (ta, tb, 0..P-1) is the z-line it owns first
   const size_t col = (size_t)(row + ex0 + le) * N + ta + P * tb;
   T rv[P], v[P], o[P];
+  double rr = 0.0;
   if (active) {
+    if (q) {
+      const T al = (T)*alpha;
 #pragma unroll
-    for (int j = 0; j < P; ++j) rv[j] = r[col + (size_t)j * L];
+      for (int j = 0; j < P; ++j) {
+        rv[j] = fma(-al, q[col + (size_t)j * L], r[col + (size_t)j * L]);
+        r[col + (size_t)j * L] = rv[j];
+        rr = fma((double)rv[j], (double)rv[j], rr);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) rv[j] = r[col + (size_t)j * L];
+    }
     fdm_forward<P, T>(a.fdmV[2][vz], rv, o);
     lds_store_line<P, T, 2>(sc, ta, tb, o);
   }
@@ -816,17 +831,21 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       rz = fma((double)rv[j], (double)o[j], rz);
     }
   }
-  if (partial) {  // r.z of the block, fixed-order tree (NT >= 128)
+  // block sums in a fixed-order tree (NT >= 128): r.z, then r.r
+  auto block_sum_to = [&](double val, double* out) {
     if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
-    sh[threadIdx.x] = rz;
+    sh[threadIdx.x] = val;
     __syncthreads();
 #pragma unroll
     for (int st = 128; st > 0; st >>= 1) {
       if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
-  }
+    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+    __syncthreads();
+  };
+  if (partial) block_sum_to(rz, partial);
+  if (q) block_sum_to(rr, partial_rr);
 }
 
 // b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
@@ -899,13 +918,15 @@ hipError_t launch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* kap
 }
 
 template <int P, typename T>
-hipError_t launch_block_jacobi(const dg_mesh& M, const T* r, T* z, double* partial, hipStream_t s) {
+hipError_t launch_block_jacobi(const dg_mesh& M, T* r, T* z, double* partial, const T* q, const double* alpha,
+                               double* partial_rr, hipStream_t s) {
   constexpr int EB = CellsPerBlock<P>::value;
   static_assert(EB * P * P >= 128 && EB * P * P <= 256, "block reduction assumes 128..256 threads");
   const int64_t G = grid_of(host_params<T>(M)[SP_APPLY]);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   const ScalarArgs<T>* ap = device_params<T>(M) + SP_APPLY;
-  hipLaunchKernelGGL((k_block_jacobi<P, T>), dim3((unsigned)G), dim3(EB * P * P), 0, s, r, z, ap, partial);
+  hipLaunchKernelGGL((k_block_jacobi<P, T>), dim3((unsigned)G), dim3(EB * P * P), 0, s, r, z, ap, partial, q, alpha,
+                     partial_rr);
   return hipGetLastError();
 }
 
@@ -941,8 +962,9 @@ hipError_t dispatch_adjoint(const dg_mesh& M, const T* g, const T* u, const T* k
 }
 
 template <typename T>
-hipError_t dispatch_block_jacobi(const dg_mesh& M, const T* r, T* z, double* partial, hipStream_t s) {
-#define DG_CALL(PP) launch_block_jacobi<PP, T>(M, r, z, partial, s)
+hipError_t dispatch_block_jacobi(const dg_mesh& M, T* r, T* z, double* partial, const T* q, const double* alpha,
+                                 double* partial_rr, hipStream_t s) {
+#define DG_CALL(PP) launch_block_jacobi<PP, T>(M, r, z, partial, q, alpha, partial_rr, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
@@ -1028,8 +1050,19 @@ hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void*
 }
 
 hipError_t block_jacobi(const dg_mesh& M, int prec, const void* r, void* z, double* partial, hipStream_t s) {
-  if (prec == DG_F64) return dispatch_block_jacobi<double>(M, (const double*)r, (double*)z, partial, s);
-  return dispatch_block_jacobi<float>(M, (const float*)r, (float*)z, partial, s);
+  // r is only read when no update is requested
+  if (prec == DG_F64)
+    return dispatch_block_jacobi<double>(M, (double*)r, (double*)z, partial, nullptr, nullptr, nullptr, s);
+  return dispatch_block_jacobi<float>(M, (float*)r, (float*)z, partial, nullptr, nullptr, nullptr, s);
+}
+
+hipError_t block_jacobi_update(const dg_mesh& M, int prec, void* r, const void* q, const double* alpha, void* z,
+                               double* partial_rz, double* partial_rr, hipStream_t s) {
+  if (!q || !alpha || !partial_rz || !partial_rr) return hipErrorInvalidValue;
+  if (prec == DG_F64)
+    return dispatch_block_jacobi<double>(M, (double*)r, (double*)z, partial_rz, (const double*)q, alpha, partial_rr,
+                                         s);
+  return dispatch_block_jacobi<float>(M, (float*)r, (float*)z, partial_rz, (const float*)q, alpha, partial_rr, s);
 }
 
 int64_t block_jacobi_blocks(const dg_mesh& M) { return grid_of(M.pd[SP_APPLY]); }

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <string>
 
 #include "solver.h"
@@ -71,6 +72,7 @@ class Solver {
       : M_(M), kappa_(kappa), s_(s), n_(M.ndofs), pc_(pc) {
     const int64_t np = pc ? std::max<int64_t>(dgi::RED_BLOCKS, dgi::block_jacobi_blocks(M)) : dgi::RED_BLOCKS;
     dev_alloc(partial_, sizeof(double) * np);
+    if (pc) dev_alloc(partial2_, sizeof(double) * np);
     dev_alloc(state_, sizeof(dgi::CgState));
     if (hipHostMalloc(&host_.p, sizeof(dgi::CgState)) != hipSuccess) {
       (void)hipGetLastError();
@@ -92,8 +94,6 @@ class Solver {
     ck(dgi::scalar_apply(M_, prec, x, y, kappa, false, s_), "apply");
   }
 
-  bool preconditioned() const { return pc_; }
-
   // z = P r and r.z reduced into the state with `op` (OP_SET_RZ or OP_BETA_PC)
   void precond(int prec, const void* r, void* z, int op) {
     ck(dgi::block_jacobi(M_, prec, r, z, partial(), s_), "preconditioner");
@@ -110,18 +110,24 @@ class Solver {
     }
   }
 
-  // one CG iteration: q = A p, x += alpha p, r -= alpha q, p = r + beta p
-  // (preconditioned: z = P r, p = z + beta p)
+  // one CG iteration: q = A p, r -= alpha q, then x += alpha p and
+  // p = r + beta p in one pass (preconditioned: the residual update runs in
+  // the preconditioner's pass, z = P r, p = z + beta p)
   void iterate(int prec, void* x, void* r, void* p, void* q, void* z, const void* kappa) {
     apply(prec, p, q, kappa);
     ck(dgi::blas_dot(p, q, prec, n_, partial(), st(), pc_ ? dgi::OP_ALPHA_PC : dgi::OP_ALPHA, s_), "p.Ap");
-    ck(dgi::blas_cg_update(x, r, p, q, prec, n_, partial(), st(), pc_ ? dgi::OP_RR : dgi::OP_BETA, s_),
-       "cg update");
     if (pc_) {
-      precond(prec, r, z, dgi::OP_BETA_PC);
-      ck(dgi::blas_xpay(z, p, prec, n_, st(), s_), "p update");
+      const double* alpha = reinterpret_cast<const double*>(reinterpret_cast<const char*>(st()) +
+                                                            offsetof(dgi::CgState, alpha));
+      const int64_t nb = dgi::block_jacobi_blocks(M_);
+      ck(dgi::block_jacobi_update(M_, prec, r, q, alpha, z, partial(), (double*)partial2_.p, s_),
+         "residual update and preconditioner");
+      ck(dgi::blas_finalize((double*)partial2_.p, nb, st(), dgi::OP_RR, s_), "r.r");
+      ck(dgi::blas_finalize(partial(), nb, st(), dgi::OP_BETA_PC, s_), "r.z");
+      ck(dgi::blas_xp_update(x, p, z, prec, n_, st(), s_), "x and p update");
     } else {
-      ck(dgi::blas_xpay(r, p, prec, n_, st(), s_), "p update");
+      ck(dgi::blas_r_update(r, q, prec, n_, partial(), st(), dgi::OP_BETA, s_), "residual update");
+      ck(dgi::blas_xp_update(x, p, r, prec, n_, st(), s_), "x and p update");
     }
   }
 
@@ -165,7 +171,7 @@ class Solver {
   hipStream_t s_;
   int64_t n_;
   bool pc_;
-  DevMem partial_, state_;
+  DevMem partial_, partial2_, state_;
   HostPinned host_;
 };
 

@@ -38,13 +38,13 @@ enum : int {
 // a.b (FP64 accumulation) reduced into the state with `op`.
 hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* partial, CgState* st, int op,
                     hipStream_t s);
-// x += alpha p, r -= alpha q, then the new r.r reduced with `op` (OP_BETA:
-// beta = r.r / rr_old, rr = r.r; OP_RR for preconditioned CG: rr = r.r).
-hipError_t blas_cg_update(void* x, void* r, const void* p, const void* q, int prec, int64_t n, double* partial,
-                          CgState* st, int op, hipStream_t s);
 // Sums nb partial sums (fixed order) and applies `op` to the state.
 hipError_t blas_finalize(const double* partial, int64_t nb, CgState* st, int op, hipStream_t s);
-hipError_t blas_xpay(const void* r, void* p, int prec, int64_t n, CgState* st, hipStream_t s);
+// r -= alpha q, then r.r reduced with `op` (OP_BETA or OP_RR).
+hipError_t blas_r_update(void* r, const void* q, int prec, int64_t n, double* partial, CgState* st, int op,
+                         hipStream_t s);
+// x += alpha p, p = z + beta p in one pass.
+hipError_t blas_xp_update(void* x, void* p, const void* z, int prec, int64_t n, CgState* st, hipStream_t s);
 // r = b - Ax, nrm2 = r.r.
 hipError_t blas_residual(const double* b, const double* Ax, double* r, int64_t n, double* partial, CgState* st,
                          hipStream_t s);
