@@ -63,3 +63,13 @@ def test_null_arguments_rejected_without_gpu(dg):
     out = ctypes.c_void_p()
     assert dg.lib.dg_mesh_create(None, None, ctypes.byref(out)) == dg.DG_ERR_ARG
     assert dg.lib.dg_solve(None, 0, None, None, None, None, None, None) < 0
+    assert dg.lib.dg_precond_apply(None, 0, None, None, None) == dg.DG_ERR_ARG
+    assert b"NULL" in dg.lib.dg_last_error()
+
+
+def test_solve_params_layout_matches_header(dg):
+    """The ctypes mirror of dg_solve_params has the header's fields in order."""
+    text = open(os.path.join(ROOT, "include", "dg.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} dg_solve_params;", text).group(1)
+    fields = re.findall(r"^\s*(?:double|int32_t)\s+(\w+);", body, re.M)
+    assert fields == [f for f, _ in dg.dg_solve_params._fields_]
