@@ -101,9 +101,12 @@ __device__ __forceinline__ double2 pair_line(double K, double L, double R, doubl
 
 // One wavefront per block; the wavefronts are independent. A wavefront
 // handles NH chunks of NC cells along x, one after the other.
+// DOT: each wavefront also writes the sum of x_i y_i over its cells (FP64,
+// fixed order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
+template <bool DOT>
 __global__ void __launch_bounds__(64)
     k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
-                    const uint32_t* __restrict__ waves) {
+                    const uint32_t* __restrict__ waves, double* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) double su[NC * LCS];  // own cells
   __shared__ __attribute__((aligned(16))) double sr[NC * LCS];  // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
@@ -111,7 +114,11 @@ __global__ void __launch_bounds__(64)
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
   const int ex00 = (int)(w0 & 0xffffu), ey = (int)(w0 >> 16), ez = (int)w1;
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  if (ex00 >= nx) return;
+  if (ex00 >= nx) {
+    if (DOT && lane == 0) partial[blockIdx.x] = 0.0;
+    return;
+  }
+  double pq = 0.0;
 
   const size_t row = (size_t)nx * ((size_t)ey + (size_t)ny * ez);
   const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in doubles
@@ -212,11 +219,18 @@ __global__ void __launch_bounds__(64)
       if (2 * p < nvalid) {
         const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl[p], zr[p], hz0, hz1);
         const double2 o = *reinterpret_cast<const double2*>(sr + 2 * LCS * p + lz);
-        if (2 * p + pc < nvalid)
-          __builtin_nontemporal_store(dvec2{wn.x * (o.x + c.x), wn.y * (o.y + c.y)},
-                                      reinterpret_cast<dvec2*>(yc + 128 * p + offz));
+        if (2 * p + pc < nvalid) {
+          const dvec2 v = {wn.x * (o.x + c.x), wn.y * (o.y + c.y)};
+          __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(yc + 128 * p + offz));
+          if (DOT) pq = fma(uz[p].y, v.y, fma(uz[p].x, v.x, pq));
+        }
       }
     }
+  }
+  if (DOT) {  // butterfly over the 64 lanes, then lane 0 writes
+#pragma unroll
+    for (int m = 32; m > 0; m >>= 1) pq += __shfl_xor(pq, m, 64);
+    if (lane == 0) partial[blockIdx.x] = pq;
   }
 }
 
@@ -298,12 +312,16 @@ hipError_t mfma_setup(dg_mesh& M) {
   return hipMemcpy(M.d_waves, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
 }
 
-hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, hipStream_t s) {
+hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, double* partial, hipStream_t s) {
   if (M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   const int64_t G = M.nwaves;
   if (G < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_q3_mfma, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                     (const uint32_t*)M.d_waves);
+  if (partial)
+    hipLaunchKernelGGL(k_apply_q3_mfma<true>, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+                       (const uint32_t*)M.d_waves, partial);
+  else
+    hipLaunchKernelGGL(k_apply_q3_mfma<false>, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+                       (const uint32_t*)M.d_waves, partial);
   return hipGetLastError();
 }
 

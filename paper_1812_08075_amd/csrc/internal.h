@@ -195,8 +195,11 @@ struct dg_mesh {
 
 namespace dgi {
 // Launchers (defined next to their kernels). They return the launch status.
+// With partial != NULL the apply also writes one partial sum of x_i y_i per
+// block (scalar_apply_blocks entries, fixed order): p.Ap for CG.
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa,
-                        bool transpose, hipStream_t s);
+                        bool transpose, hipStream_t s, double* partial = nullptr);
+int64_t scalar_apply_blocks(const dg_mesh& M, int prec, bool kappa);
 // Recomputes the face constants fA, fB of the folded tables from c_cons, c_sym.
 template <typename T>
 void derive_face_constants(ScalarArgs<T>& a);
@@ -218,7 +221,7 @@ inline bool block_jacobi_supported(const dg_mesh& M) { return M.pd[SP_APPLY].fdm
 hipError_t scalar_params_upload(dg_mesh& M);
 // Matrix-core apply of the p = 4, FP64, kappa = 1 operator (variant SP_APPLY or SP_APPLY_T).
 bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa);
-hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, hipStream_t s);
+hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, double* partial, hipStream_t s);
 // Builds and uploads the wavefront table of the matrix-core apply (M.d_waves).
 hipError_t mfma_setup(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);

@@ -404,17 +404,20 @@ __device__ __forceinline__ void neighbor_lines(const T* __restrict__ s, const T*
   }
 }
 
-template <int P, typename T, bool KAPPA>
+// DOT: every block also writes the sum of x_i y_i over its cells (FP64, fixed
+// order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
+template <int P, typename T, bool KAPPA, bool DOT>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
-                   const ScalarArgs<T>* __restrict__ ap) {
+                   const ScalarArgs<T>* __restrict__ ap, double* __restrict__ partial) {
   const ScalarArgs<T>& a = *ap;
   constexpr int EB = CellsPerBlock<P>::value;
-  constexpr int L = P * P, N = P * P * P;
+  constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
+  static_assert(EB * Ly::NP * sizeof(T) >= 256 * sizeof(double), "reduction scratch");
   __shared__ T sx[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
-  __shared__ T sy[EB * Ly::NP];  // x-line results, then += y-line results
+  __shared__ __attribute__((aligned(16))) T sy[EB * Ly::NP];  // x-line results, then += y-line results
 
   const BlockCoord bc = block_coord(a);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -476,11 +479,29 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     line_work<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
   }
   __syncthreads();
+  double pq = 0.0;
   if (active) {
     const int lo = le * Ly::NP + ta + Ly::S1 * tb;
     T* __restrict__ ye = y + e * N + ta + P * tb;
 #pragma unroll
-    for (int j = 0; j < P; ++j) ye[j * L] = fma(wt, out2[j], sy[lo + j * Ly::S2]);
+    for (int j = 0; j < P; ++j) {
+      const T v = fma(wt, out2[j], sy[lo + j * Ly::S2]);
+      ye[j * L] = v;
+      if (DOT) pq = fma((double)sx[lo + j * Ly::S2], (double)v, pq);
+    }
+  }
+  if (DOT) {  // fixed-order tree over the block (NT in [128, 256]), sy as scratch
+    double* sh = reinterpret_cast<double*>(sy);
+    __syncthreads();
+    if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
+    sh[threadIdx.x] = pq;
+    __syncthreads();
+#pragma unroll
+    for (int st = 128; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
   }
 }
 
@@ -890,15 +911,21 @@ int64_t grid_of(const ScalarArgs<T>& a) {
 }
 
 template <int P, typename T>
-hipError_t launch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, hipStream_t s) {
+hipError_t launch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, double* partial,
+                        hipStream_t s) {
   constexpr int EB = CellsPerBlock<P>::value;
   const int64_t G = grid_of(host_params<T>(M)[variant]);
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   const ScalarArgs<T>* ap = device_params<T>(M) + variant;
-  if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, ap);
+  const dim3 grid((unsigned)G), block(EB * P * P);
+  if (kappa && partial)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, true>), grid, block, 0, s, x, y, kappa, ap, partial);
+  else if (kappa)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+  else if (partial)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, true>), grid, block, 0, s, x, y, kappa, ap, partial);
   else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false>), dim3((unsigned)G), dim3(EB * P * P), 0, s, x, y, kappa, ap);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
   return hipGetLastError();
 }
 
@@ -947,8 +974,9 @@ int adjoint_cells_per_block(int p) { return 128 / (p * p) > 0 ? 128 / (p * p) : 
   }
 
 template <typename T>
-hipError_t dispatch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, hipStream_t s) {
-#define DG_CALL(PP) launch_apply<PP, T>(M, variant, x, y, kappa, s)
+hipError_t dispatch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T* kappa, double* partial,
+                          hipStream_t s) {
+#define DG_CALL(PP) launch_apply<PP, T>(M, variant, x, y, kappa, partial, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
@@ -1033,11 +1061,18 @@ void fill_params(const ScalarArgs<T>& base, const Tables1D& tab, int p, ScalarAr
 }  // namespace
 
 hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, const void* kappa, bool transpose,
-                        hipStream_t s) {
+                        hipStream_t s, double* partial) {
   const int v = transpose ? SP_APPLY_T : SP_APPLY;
-  if (mfma_apply_supported(M, prec, kappa != nullptr)) return mfma_apply(M, v, (const double*)x, (double*)y, s);
-  if (prec == DG_F64) return dispatch_apply<double>(M, v, (const double*)x, (double*)y, (const double*)kappa, s);
-  return dispatch_apply<float>(M, v, (const float*)x, (float*)y, (const float*)kappa, s);
+  if (mfma_apply_supported(M, prec, kappa != nullptr))
+    return mfma_apply(M, v, (const double*)x, (double*)y, partial, s);
+  if (prec == DG_F64)
+    return dispatch_apply<double>(M, v, (const double*)x, (double*)y, (const double*)kappa, partial, s);
+  return dispatch_apply<float>(M, v, (const float*)x, (float*)y, (const float*)kappa, partial, s);
+}
+
+int64_t scalar_apply_blocks(const dg_mesh& M, int prec, bool kappa) {
+  if (mfma_apply_supported(M, prec, kappa)) return M.nwaves;
+  return grid_of(M.pd[SP_APPLY]);
 }
 
 hipError_t scalar_adjoint(const dg_mesh& M, int prec, const void* g, const void* u, const void* kappa, void* ATg,

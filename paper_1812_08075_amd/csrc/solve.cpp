@@ -70,7 +70,11 @@ class Solver {
  public:
   Solver(const dg_mesh& M, const void* kappa, bool pc, hipStream_t s)
       : M_(M), kappa_(kappa), s_(s), n_(M.ndofs), pc_(pc) {
-    const int64_t np = pc ? std::max<int64_t>(dgi::RED_BLOCKS, dgi::block_jacobi_blocks(M)) : dgi::RED_BLOCKS;
+    const bool kap = kappa != nullptr;
+    const int64_t napply =
+        std::max(dgi::scalar_apply_blocks(M, DG_F64, kap), dgi::scalar_apply_blocks(M, DG_F32, kap));
+    int64_t np = std::max<int64_t>(dgi::RED_BLOCKS, napply);
+    if (pc) np = std::max(np, dgi::block_jacobi_blocks(M));
     dev_alloc(partial_, sizeof(double) * np);
     if (pc) dev_alloc(partial2_, sizeof(double) * np);
     dev_alloc(state_, sizeof(dgi::CgState));
@@ -110,12 +114,15 @@ class Solver {
     }
   }
 
-  // one CG iteration: q = A p, r -= alpha q, then x += alpha p and
+  // one CG iteration: q = A p (with p.q), r -= alpha q, then x += alpha p and
   // p = r + beta p in one pass (preconditioned: the residual update runs in
   // the preconditioner's pass, z = P r, p = z + beta p)
   void iterate(int prec, void* x, void* r, void* p, void* q, void* z, const void* kappa) {
-    apply(prec, p, q, kappa);
-    ck(dgi::blas_dot(p, q, prec, n_, partial(), st(), pc_ ? dgi::OP_ALPHA_PC : dgi::OP_ALPHA, s_), "p.Ap");
+    // q = A p with p.q reduced per block by the apply kernel itself
+    ck(dgi::scalar_apply(M_, prec, p, q, kappa, false, s_, partial()), "apply");
+    ck(dgi::blas_finalize(partial(), dgi::scalar_apply_blocks(M_, prec, kappa != nullptr), st(),
+                          pc_ ? dgi::OP_ALPHA_PC : dgi::OP_ALPHA, s_),
+       "p.Ap");
     if (pc_) {
       const double* alpha = reinterpret_cast<const double*>(reinterpret_cast<const char*>(st()) +
                                                             offsetof(dgi::CgState, alpha));
