@@ -131,9 +131,12 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
   constexpr int RA = (6 * NF > 10 * N) ? 6 * NF : 10 * N;
   // staging of the pressure contractions: cell stages s1 [P KP^2], s2 [P^2 KP] and
   // face-trace stages c1 [12 KP^2], c2 [12 P KP] live side by side; the test
-  // stages (KP P^2 + 6 KP P + KP^2 P + 6 KP^2) reuse the space later
+  // stages (KP P^2 + 6 KP P + KP^2 P + 6 KP^2) reuse the space later. Both
+  // run while the face coefficients are dead (before the faces' flux stage,
+  // after the velocity test functions), so the staging shares their space.
   constexpr int TMP = P * KP * KP + P * P * KP + 12 * KP * KP + 12 * P * KP;
   static_assert(KP * P * P + 6 * KP * P + KP * KP * P + 6 * KP * KP <= TMP, "pressure staging");
+  static_assert(TMP <= 9 * NF, "pressure staging inside the face coefficients");
   __shared__ double su[3 * N];        // velocity
   __shared__ double sp[NQ];           // pressure
   __shared__ double sX[24];           // own corners
@@ -142,11 +145,12 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
   __shared__ double spq[N];           // pressure at the quadrature points
   __shared__ double fpT[NF], fpN[NF]; // pressure traces (own, neighbour) at the face points
   __shared__ double regA[RA];         // faces: velocity traces fT[3][NF], fN[3][NF]; then cell residual sR[9][N], sRp[N]
-  __shared__ double fV[3 * NF];       // face coefficients of v_c
-  __shared__ double fRg[3 * NF];      // face coefficients of grad v_c . nu
-  __shared__ double fJn[3 * NF];      // J^{-1} nu at the face points
+  __shared__ double fcoef[9 * NF];    // fV, fRg, fJn (below); pressure staging `tmp` at other times
   __shared__ double fQ[NF];           // face coefficients of q
-  __shared__ double tmp[TMP];
+  double* fV = fcoef;                 // face coefficients of v_c
+  double* fRg = fcoef + 3 * NF;       // face coefficients of grad v_c . nu
+  double* fJn = fcoef + 6 * NF;       // J^{-1} nu at the face points
+  double* tmp = fcoef;
   double* fT = regA;
   double* fN = regA + 3 * NF;
   double* sR = regA;
@@ -480,7 +484,9 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
     for (int c = 0; c < 3; ++c) y[base + c * N + i] = acc[c];
   }
   // pressure test functions by sum factorization: cell (A_p^T x3) R_p and, per
-  // face, e_p(s) (x) (A_p^T x A_p^T) Q_f
+  // face, e_p(s) (x) (A_p^T x A_p^T) Q_f; the staging overwrites the face
+  // coefficients, read above by every thread
+  __syncthreads();
   double* t1b = tmp;                      // [j0][q1][q2]
   double* u1 = tmp + KP * P * P;          // [f][ja][pb]
   for (int i = t; i < KP * P * P; i += NT) {
