@@ -104,9 +104,9 @@ __device__ __forceinline__ double2 pair_line(double K, double L, double R, doubl
 // DOT: each wavefront also writes the sum of x_i y_i over its cells (FP64,
 // fixed order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
 template <bool DOT>
-__global__ void __launch_bounds__(64)
-    k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
-                    const uint32_t* __restrict__ waves, double* __restrict__ partial) {
+__device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, double* __restrict__ y,
+                                              const ScalarArgs<double>* __restrict__ ap,
+                                              const uint32_t* __restrict__ waves, double* __restrict__ partial) {
   __shared__ __attribute__((aligned(16))) double su[NC * LCS];  // own cells
   __shared__ __attribute__((aligned(16))) double sr[NC * LCS];  // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
@@ -234,6 +234,22 @@ __global__ void __launch_bounds__(64)
   }
 }
 
+// The apply, with a register budget for five wavefronts per SIMD (94 VGPRs,
+// the matrix-core results in architectural VGPRs), and the conjugate-gradient
+// variant with the fused p.Ap.
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
+    k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
+                    const uint32_t* __restrict__ waves) {
+  apply_q3_wave<false>(x, y, ap, waves, nullptr);
+}
+
+__global__ void __launch_bounds__(64)
+    k_apply_q3_mfma_dot(const double* __restrict__ x, double* __restrict__ y,
+                        const ScalarArgs<double>* __restrict__ ap, const uint32_t* __restrict__ waves,
+                        double* __restrict__ partial) {
+  apply_q3_wave<true>(x, y, ap, waves, partial);
+}
+
 // XCD-aware renumbering of hardware blocks (block b runs on XCD b % 8).
 int xcd_swizzle_host(int b, int G) {
   const int q = G >> 3, r = G & 7;
@@ -317,11 +333,11 @@ hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y,
   const int64_t G = M.nwaves;
   if (G < 1) return hipSuccess;
   if (partial)
-    hipLaunchKernelGGL(k_apply_q3_mfma<true>, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+    hipLaunchKernelGGL(k_apply_q3_mfma_dot, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
                        (const uint32_t*)M.d_waves, partial);
   else
-    hipLaunchKernelGGL(k_apply_q3_mfma<false>, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                       (const uint32_t*)M.d_waves, partial);
+    hipLaunchKernelGGL(k_apply_q3_mfma, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+                       (const uint32_t*)M.d_waves);
   return hipGetLastError();
 }
 
