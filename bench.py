@@ -122,9 +122,20 @@ def bench_adjoint(dg, w, steps, warmup):
     return rates(info, ms, 0, nbytes=info.bytes_adjoint, flops=info.flops_adjoint)
 
 
-def cpu_baseline(target_s=12.0):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+def cpu_baseline(target_s=12.0, single_s=4.0):
     """The oracle's deduplicated block-sparse SpMV of the Q3 operator, timed on
-    the host on a 24^3 copy of the benchmark mesh (a bounded sample)."""
+    the host on a 24^3 copy of the benchmark mesh (a bounded sample), with the
+    BLAS thread pool as configured and, briefly, with one thread."""
     import numpy as np
     import workloads
     from oracle import ScalarDG, problem_from_workload
@@ -133,20 +144,31 @@ def cpu_baseline(target_s=12.0):
     A = ScalarDG(problem_from_workload(w, n=n)).assemble("dedup")
     x = workloads.inputs(w.scaled(n), "x")
     A.matvec(x)
-    reps, t0 = 0, time.perf_counter()
-    while time.perf_counter() - t0 < target_s:
-        A.matvec(x)
-        reps += 1
-    el = time.perf_counter() - t0
+
+    def rate(seconds):
+        reps, t0 = 0, time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            A.matvec(x)
+            reps += 1
+        return reps, time.perf_counter() - t0
+
+    reps, el = rate(target_s)
+    ndofs = n ** 3 * 64
+    one = None
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        with threadpool_limits(limits=1):
+            r1, e1 = rate(single_s)
+        one = ndofs * r1 / e1
     except Exception:  # threadpoolctl missing: BLAS thread count unknown, report the host count
         cores = os.cpu_count()
-    ndofs = n ** 3 * 64
-    return {"value": ndofs * reps / el, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"Q3 SIPG dedup-BSR SpMV (numpy/BLAS) on a {n}^3 copy of the 64^3 mesh, "
-                      f"{reps} applies in {el:.1f} s; host has {os.cpu_count()} logical CPUs"}
+    out = {"value": ndofs * reps / el, "unit": "DOFs/s", "cores": int(cores), "kind": "oracle",
+           "sample": f"Q3 SIPG dedup-BSR SpMV (numpy/BLAS) on a {n}^3 copy of the 64^3 mesh, "
+                     f"{reps} applies in {el:.1f} s; host: {os.cpu_count()} logical CPUs, {cpu_model()}"}
+    if one is not None:
+        out["value_1thread"] = one
+    return out
 
 
 def bench_precond(dg, w, prec, steps, warmup):
