@@ -26,9 +26,15 @@
 //    with the same rows onto the own line only. Each face is thus evaluated
 //    by both its cells (element-centric): every output value has exactly one
 //    writer, there are no atomics, and results are bitwise reproducible.
+//  * With kappa = 1 in FP64 the three stages of a direction and both face
+//    terms are applied as fixed 1D line operators, out = K u + L u_left +
+//    R u_right (K in even/odd form, L and R of rank 2; built on the host);
+//    FP32 and kappa per point run the stages as above.
 //  * A block is a chunk of up to EB consecutive cells of one x-row, so its
-//    cells are contiguous in memory (one coalesced load into LDS) and
-//    x-neighbours inside the chunk are read from LDS. Blocks are swept in
+//    cells are contiguous in memory: each thread copies its own node column
+//    of its cell into LDS (one load per z-plane, the lanes of a cell reading
+//    one contiguous plane), and x-neighbours inside the chunk are read from
+//    LDS. Blocks are swept in
 //    the order (slab of z-planes, y, z within the slab, chunk) and the block
 //    order is made XCD-aware (each XCD walks one contiguous range of the
 //    sweep), so the y- and z-neighbour lines a block reads were loaded
@@ -38,7 +44,11 @@
 //    conflicts), the z line stays in registers; the sum is written once.
 //  * The same kernel applies A^T: swapping the coefficients of the two
 //    non-symmetric face terms (consistency term and theta term) transposes
-//    the face bilinear form; the cell terms are symmetric.
+//    the face bilinear form; the cell terms are symmetric. A template variant
+//    also reduces x.y per block (the p.Ap of the conjugate-gradient solvers).
+//  * Also here: the adjoint (A^T g and dL/dkappa in one pass), the
+//    block-Jacobi preconditioner (each cell's diagonal block inverted by fast
+//    diagonalization) and the load vector.
 #include "internal.h"
 
 namespace dgi {
