@@ -146,3 +146,28 @@ def test_zero_rhs(gpu_lib):
     x = torch.ones_like(b)
     st, info = dg.dg_solve(mesh.handle, 1, b, x)
     assert st == dg.DG_OK and float(x.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("shape", [(5, 4, 3), (11, 3, 2)])
+@pytest.mark.parametrize("precond", [0, 1])
+def test_q3_cg_matches_oracle(gpu_lib, shape, precond):
+    """k = 3 in FP64 with kappa = 1, where p.Ap comes from the matrix-core
+    kernel's fused partial sums (rows ending in a partial chunk): the CG and
+    preconditioned-CG iteration counts and solutions agree with the oracle's."""
+    from oracle import block_jacobi, pcg
+    dg = gpu_lib
+    print(f"case: Q3 CG shape={shape} precond={precond}", flush=True)
+    mesh = dg.Mesh(dg.make_desc(*shape, k=3))
+    bh = workloads.uniform(mesh.ndofs, 77)
+    b = torch.from_numpy(bh).cuda()
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 0, b, x, rtol=1e-8, check_every=1, precond=precond)
+    assert st == dg.DG_OK, dg.lib.dg_last_error()
+    A = ScalarDG(Problem(*shape, k=3)).assemble()
+    if precond:
+        xo, its, _ = pcg(A.matvec, lambda v: block_jacobi(A, v), bh, rtol=1e-8)
+    else:
+        xo, its, _ = cg(A.matvec, bh, rtol=1e-8)
+    assert abs(info.iterations - its) <= max(2, its // 50), (info.iterations, its)
+    xg = x.cpu().numpy()
+    assert np.linalg.norm(xg - xo) <= 1e-6 * np.linalg.norm(xo)
