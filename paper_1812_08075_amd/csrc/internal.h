@@ -85,9 +85,9 @@ struct alignas(16) ScalarArgs {
   uint32_t mask;       // Dirichlet sides, bit 2d+s
   int32_t kappa_face_one;
   // block order: a block is a chunk of up to EB consecutive cells of one x-row;
-  // blocks are swept as (slab of sz z-planes, y, z within the slab, chunk)
+  // each XCD sweeps one region of the mesh (x and z split, y outermost inside)
   int32_t nchunk;      // chunks per x-row
-  int32_t sz;          // z-planes per slab
+  int32_t pad_sweep;
   // per hardware block: (first cell's x index | y << 16, z) of its chunk, in the
   // sweep order with the XCD renumbering applied (table written at mesh creation)
   const uint32_t* blocks;

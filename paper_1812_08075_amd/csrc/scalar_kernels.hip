@@ -34,12 +34,12 @@
 //    cells are contiguous in memory: each thread copies its own node column
 //    of its cell into LDS (one load per z-plane, the lanes of a cell reading
 //    one contiguous plane), and x-neighbours inside the chunk are read from
-//    LDS. Blocks are swept in
-//    the order (slab of z-planes, y, z within the slab, chunk) and the block
-//    order is made XCD-aware (each XCD walks one contiguous range of the
-//    sweep), so the y- and z-neighbour lines a block reads were loaded
-//    shortly before by another block of the same XCD and are served by its
-//    L2: HBM sees about one read of x (plus kappa) and one write of y.
+//    LDS. Each XCD sweeps one region of the mesh (x and z split to read the
+//    fewest cells across region boundaries, y unsplit; inside a region y
+//    outermost, then z, then x), so the y- and z-neighbour lines a block
+//    reads were loaded shortly before by another block of the same XCD and
+//    are served by its L2: HBM sees about one read of x (plus kappa) and one
+//    write of y, plus the region boundaries.
 //  * The x and y line results go through LDS (padded strides against bank
 //    conflicts), the z line stays in registers; the sum is written once.
 //  * The same kernel applies A^T: swapping the coefficients of the two
@@ -897,7 +897,6 @@ __global__ void k_scalar_load(const T* __restrict__ f, T* __restrict__ b, const 
 template <typename T>
 int64_t sweep_grid(ScalarArgs<T>& a, int eb) {
   a.nchunk = (a.n[0] + eb - 1) / eb;
-  a.sz = a.n[2] >= 8 ? a.n[2] / 8 : 1;
   return (int64_t)a.nchunk * a.n[1] * a.n[2];
 }
 
@@ -1031,21 +1030,47 @@ int xcd_swizzle(int b, int G) {
   return xcd * q + std::min(xcd, r) + idx;
 }
 
-// Block table of a sweep grid (chunks of eb cells of every x-row, swept as
-// (slab of sz z-planes, y, z within the slab, chunk)), indexed by hardware block.
-std::vector<uint32_t> block_table(int nx, int ny, int nz, int eb, int sz) {
+// Block table of a sweep grid (chunks of eb cells of every x-row). Each XCD
+// (its own L2) sweeps one region of the mesh: x (in whole chunks) and z are
+// split so that the fewest cells are read across region boundaries, y is not
+// split (the sweep front, the region's x-z cross-section, stays small), and
+// inside a region the blocks run y-outermost, then z, then x. Hardware block
+// b runs on XCD b % 8 and takes position swizzle(b) of that order.
+std::vector<uint32_t> block_table(int nx, int ny, int nz, int eb) {
   const int nc = (nx + eb - 1) / eb;
   const int G = nc * ny * nz;
+  int best[2] = {1, 1};
+  double best_cost = -1;
+  for (int rx = 1; rx <= 8; rx *= 2) {
+    const int rz = 8 / rx;
+    if (rx > nc || rz > nz) continue;
+    const double cost = (double)(rx - 1) * ny * nz + (double)(rz - 1) * nx * ny;
+    if (best_cost < 0 || cost < best_cost) {
+      best_cost = cost;
+      best[0] = rx;
+      best[1] = rz;
+    }
+  }
+  auto bound = [](int n, int r, int i) { return (int)(((int64_t)n * i) / r); };
+  std::vector<uint32_t> order(2 * (size_t)G);
+  size_t t = 0;
+  for (int gz = 0; gz < best[1]; ++gz)
+    for (int gx = 0; gx < best[0]; ++gx) {
+      const int c0 = bound(nc, best[0], gx), c1 = bound(nc, best[0], gx + 1);
+      const int z0 = bound(nz, best[1], gz), z1 = bound(nz, best[1], gz + 1);
+      for (int yy = 0; yy < ny; ++yy)
+        for (int zz = z0; zz < z1; ++zz)
+          for (int cc = c0; cc < c1; ++cc) {
+            order[2 * t] = (uint32_t)(cc * eb) | ((uint32_t)yy << 16);
+            order[2 * t + 1] = (uint32_t)zz;
+            ++t;
+          }
+    }
   std::vector<uint32_t> tab(2 * (size_t)G);
-  const int per_slab = nc * ny * sz;
   for (int b = 0; b < G; ++b) {
-    const int t = xcd_swizzle(b, G);
-    const int slab = t / per_slab, rem = t - slab * per_slab;
-    const int hz = std::min(sz, nz - slab * sz);
-    const int ey = rem / (nc * hz), rem2 = rem - ey * nc * hz;
-    const int ezi = rem2 / nc, chunk = rem2 - ezi * nc;
-    tab[2 * (size_t)b] = (uint32_t)(chunk * eb) | ((uint32_t)ey << 16);
-    tab[2 * (size_t)b + 1] = (uint32_t)(slab * sz + ezi);
+    const int l = xcd_swizzle(b, G);
+    tab[2 * (size_t)b] = order[2 * (size_t)l];
+    tab[2 * (size_t)b + 1] = order[2 * (size_t)l + 1];
   }
   return tab;
 }
@@ -1122,11 +1147,10 @@ hipError_t scalar_params_upload(dg_mesh& M) {
   fill_params(M.sf, M.tab, M.p, M.pf);
   // block tables: apply grid, then adjoint grid
   const std::vector<uint32_t> ta =
-      block_table(M.pd[SP_APPLY].n[0], M.pd[SP_APPLY].n[1], M.pd[SP_APPLY].n[2], apply_cells_per_block(M.p),
-                  M.pd[SP_APPLY].sz);
+      block_table(M.pd[SP_APPLY].n[0], M.pd[SP_APPLY].n[1], M.pd[SP_APPLY].n[2], apply_cells_per_block(M.p));
   const std::vector<uint32_t> tj =
       block_table(M.pd[SP_ADJOINT].n[0], M.pd[SP_ADJOINT].n[1], M.pd[SP_ADJOINT].n[2],
-                  adjoint_cells_per_block(M.p), M.pd[SP_ADJOINT].sz);
+                  adjoint_cells_per_block(M.p));
   hipError_t e = hipMalloc(&M.d_blocks, sizeof(uint32_t) * (ta.size() + tj.size()));
   if (e != hipSuccess) return e;
   e = hipMemcpy(M.d_blocks, ta.data(), sizeof(uint32_t) * ta.size(), hipMemcpyHostToDevice);
