@@ -49,22 +49,29 @@ def time_applies(fn, steps, warmup, stream):
 
 
 def copy_reference():
-    """Achieved HBM bandwidth of a plain device copy of 8 x 134 MB (torch's copy
-    kernel), timed like the applies: the same-box reference for the fractions."""
+    """Achieved HBM bandwidth of a plain device copy of 134 MB (torch's copy
+    kernel), timed like the applies: the same-box reference for the fractions.
+    `gbs` rotates 4 source/destination pairs (1.07 GB, beyond the 256 MB MALL);
+    `gbs_one_pair` copies one pair over and over, the reuse pattern of the
+    benchmark step (one x, one y)."""
     import torch
     n = 16777216
     src = [torch.ones(n, dtype=torch.float64, device="cuda") for _ in range(4)]
     dst = [torch.empty_like(src[0]) for _ in range(4)]
     stream = torch.cuda.current_stream()
-    it = [0]
+    out = {}
+    for key, npair in (("", 4), ("_one_pair", 1)):
+        it = [0]
 
-    def step():
-        i = it[0] % 4
-        it[0] += 1
-        dst[i].copy_(src[i])
+        def step():
+            i = it[0] % npair
+            it[0] += 1
+            dst[i].copy_(src[i])
 
-    ms = time_applies(step, 40, 4, stream)
-    return {"ms": round(ms, 5), "gbs": 2 * n * 8 / (ms * 1e-3) / 1e9}
+        ms = time_applies(step, 40, 4, stream)
+        out["ms" + key] = round(ms, 5)
+        out["gbs" + key] = 2 * n * 8 / (ms * 1e-3) / 1e9
+    return out
 
 
 def rates(info, ms, prec, nbytes=None, flops=None):
