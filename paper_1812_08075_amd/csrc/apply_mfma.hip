@@ -28,16 +28,22 @@
 //    lines of both cells go through one product.
 //  * The x direction needs i0 in lane bits 4-5, one cell per register
 //    ("x layout": lane = i1 + 4 i2 + 16 i0). The own cells are staged in LDS
-//    and read back in the x and y layouts; the x-lines of the cells beyond
+//    and read back in the x, y and z layouts; the x-lines of the cells beyond
 //    both ends of the chunk are read from global memory. The LDS layout is
 //    padded (i1, i2 and cell strides 4, 18, 70 doubles) against bank
 //    conflicts of the three access layouts.
-//  * A wavefront owns NH = 2 steps of NC = 4 x-consecutive cells. Per step
-//    it issues all of its global reads first: the own cells and the z- and
-//    y-neighbour cells in pairs, and the two x-end lines. The A-operand
-//    entries of the nine interior-cell operators and the two nodes' tensor
-//    weights form one 96-byte record per lane, read once per wavefront;
-//    boundary cells read their own K variant. Wavefronts are independent
+//  * A wavefront owns a chunk of NC = 4 x-consecutive cells and marches
+//    along y over up to 16 rows of it (the count comes with its table
+//    entry). Two LDS buffers hold the rows y and y + 1: per step the
+//    wavefront reads from global memory only the row y + 1 (in the z
+//    layout, into the buffer that held row y - 1), the z-neighbour cells
+//    and the two x-end lines; the y-neighbour lines come from LDS, row
+//    y - 1 read before it is replaced. That is 8 global loads per 4 cells
+//    where reading the y-neighbours from L2 takes 12, and the load issue
+//    rate, not the bytes, is what limits this kernel. The A-operand entries
+//    of the nine interior-cell operators and the two nodes' tensor weights
+//    form one 96-byte record per lane, read once per wavefront; boundary
+//    cells and rows read their own K variant. Wavefronts are independent
 //    (one per block).
 //  * Results: the x results are written to LDS, the y results added to them
 //    in the y-pair layout, and the z results added on reading them back in
@@ -47,9 +53,9 @@
 //  * Each XCD (its own L2) sweeps one region of the mesh: x and z are split
 //    so that the fewest cells are read across region boundaries, y is not
 //    split, and inside a region the wavefronts run y-outermost, then z,
-//    then x, so that the y- and z-neighbour cells are still in the XCD's L2.
-//    The hardware dispatches block b to XCD b mod 8; a table built on the
-//    host maps blocks to wavefront positions accordingly.
+//    then x, so that the z-neighbour cells are still in the XCD's L2. The
+//    hardware dispatches block b to XCD b mod 8; a table built on the host
+//    maps blocks to wavefront positions accordingly.
 #include <algorithm>
 #include <vector>
 
@@ -59,7 +65,7 @@ namespace dgi {
 namespace {
 
 constexpr int NC = 4;            // cells per step (consecutive along x): two pairs
-constexpr int NH = 2;            // steps per wavefront
+constexpr int NYMAX = 16;        // most rows along y per wavefront
 // LDS node (i0, i1, i2) of cell c at c LCS + i2 LPS + i1 LIS + i0 (doubles):
 // padded against bank conflicts of the three access layouts
 constexpr int LIS = 4, LPS = 18, LCS = 70;
@@ -100,37 +106,36 @@ __device__ __forceinline__ double2 pair_line(double K, double L, double R, doubl
 }
 
 // One wavefront per block; the wavefronts are independent. A wavefront
-// handles NH chunks of NC cells along x, one after the other.
+// handles NC cells along x in each of its rows along y, one row per step.
 // DOT: each wavefront also writes the sum of x_i y_i over its cells (FP64,
 // fixed order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
 template <bool DOT>
 __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, double* __restrict__ y,
                                               const ScalarArgs<double>* __restrict__ ap,
                                               const uint32_t* __restrict__ waves, double* __restrict__ partial) {
-  __shared__ __attribute__((aligned(16))) double su[NC * LCS];  // own cells
-  __shared__ __attribute__((aligned(16))) double sr[NC * LCS];  // x results, then x + y results
+  __shared__ __attribute__((aligned(16))) double su[2 * NC * LCS];  // own cells of rows y and y + 1
+  __shared__ __attribute__((aligned(16))) double sr[NC * LCS];      // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
   const int lane = threadIdx.x;
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
-  const int ex00 = (int)(w0 & 0xffffu), ey = (int)(w0 >> 16), ez = (int)w1;
+  const int ex0 = (int)(w0 & 0xffffu), ey0 = (int)(w0 >> 16), ez = (int)(w1 & 0xffffu);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  if (ex00 >= nx) {
+  if (ex0 >= nx || ey0 >= ny) {
     if (DOT && lane == 0) partial[blockIdx.x] = 0.0;
     return;
   }
   double pq = 0.0;
+  const int nvalid = min(NC, nx - ex0);
+  const int nsteps = min((int)(w1 >> 16), ny - ey0);
+  const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
+  const size_t row0 = (size_t)nx * ((size_t)ey0 + (size_t)ny * ez);
+  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;
+  const bool hz0 = ez > 0, hz1 = ez < nz - 1;
 
-  const size_t row = (size_t)nx * ((size_t)ey + (size_t)ny * ez);
-  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in doubles
-  const bool hy0 = ey > 0, hy1 = ey < ny - 1, hz0 = ez > 0, hz1 = ez < nz - 1;
-
-  // pair layouts: lane = h + 2 t + 8 c + 16 n; node offsets of the lane's first node
   const int h = lane & 1, t = (lane >> 1) & 3, pc = (lane >> 3) & 1, n = lane >> 4;
-  const int offz = 2 * h + 4 * t + 16 * n + 64 * pc;  // node (2h, t, n) of cell pc
-  const int offy = 2 * h + 16 * t + 4 * n + 64 * pc;  // node (2h, n, t) of cell pc
-  // x layout: lane = i1 + 4 i2 + 16 i0
+  const int offz = 2 * h + 4 * t + 16 * n + 64 * pc;
   const int offx = (lane >> 4) + 4 * (lane & 3) + 16 * ((lane >> 2) & 3);
-  const int lz = 2 * h + LIS * t + LPS * n + LCS * pc;  // LDS offsets of the same nodes
+  const int lz = 2 * h + LIS * t + LPS * n + LCS * pc;
   const int ly = 2 * h + LPS * t + LIS * n + LCS * pc;
   const int lx = (lane >> 4) + LIS * (lane & 3) + LPS * ((lane >> 2) & 3);
 
@@ -138,53 +143,63 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
   const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
 #pragma unroll
   for (int k = 0; k < 6; ++k) rec[k] = lr[k];
-  const int ai = 4 * (lane & 3) + (lane >> 4);  // A operand: entry (lane % 4, lane / 16)
+  const int ai = 4 * (lane & 3) + (lane >> 4);
   const uint32_t mask = a.mask;
-  const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
   const double Kx_int = rec[0].x, Lx = rec[0].y, Rx = rec[1].x;
-  double Ky = rec[1].y;
+  const double Ky_int = rec[1].y;
   const double Ly = rec[2].x, Ry = rec[2].y;
   double Kz = rec[3].x;
   const double Lz = rec[3].y, Rz = rec[4].x;
   const double2 wn = rec[5];
-  if (vy != 0) Ky = a.Km[1][vy][ai];
   if (vz != 0) Kz = a.Km[2][vz][ai];
 
-  for (int hh = 0; hh < NH; ++hh) {
-    const int ex0 = ex00 + NC * hh;
-    const int nvalid = min(NC, nx - ex0);
-    if (nvalid <= 0) break;
-    const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
-    const double* __restrict__ xc = x + (row + ex0) * 64;
+  // own row ey0 to buffer 0, row ey0 - 1 to buffer 1 (invalid or absent
+  // cells as zeros)
+  {
+    const double* __restrict__ xc = x + (row0 + ex0) * 64;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const bool v = 2 * p + pc < nvalid;
+      const double2 u0 = load2(xc + 128 * p + offz, v);
+      const double2 um = load2(xc - sy + 128 * p + offz, v && ey0 > 0);
+      *reinterpret_cast<double2*>(su + 2 * LCS * p + lz) = u0;
+      *reinterpret_cast<double2*>(su + NC * LCS + 2 * LCS * p + lz) = um;
+    }
+  }
 
-    double2 uz[2], zl[2], zr[2], yl[2], yr[2];
+  for (int s = 0; s < nsteps; ++s) {
+    const int ey = ey0 + s;
+    const bool hy0 = ey > 0, hy1 = ey < ny - 1;
+    const size_t row = row0 + (size_t)s * nx;
+    const double* __restrict__ xc = x + (row + ex0) * 64;
+    double* __restrict__ cur = su + (s & 1) * (NC * LCS);
+    double* __restrict__ oth = su + ((s + 1) & 1) * (NC * LCS);
+
+    double2 nr[2], zl[2], zr[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const bool v = 2 * p + pc < nvalid;
       const double* b = xc + 128 * p;
-      uz[p] = load2(b + offz, v);
+      nr[p] = load2(b + sy + offz, v && hy1);
       zl[p] = load2(b - sz + offz, v && hz0);
       zr[p] = load2(b + sz + offz, v && hz1);
-      yl[p] = load2(b - sy + offy, v && hy0);
-      yr[p] = load2(b + sy + offy, v && hy1);
     }
     const double xl = hxl ? xc[offx - 64] : 0.0;
     const double xr = hxr ? xc[64 * nvalid + offx] : 0.0;
 
-    // own cells to LDS (invalid cells as zeros), back in the x and y layouts
-    if (hh > 0) __syncthreads();
+    // row ey - 1 in the y layout, before the next row replaces it
+    double2 yl[2];
 #pragma unroll
-    for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(su + 2 * LCS * p + lz) = uz[p];
+    for (int p = 0; p < 2; ++p) yl[p] = *reinterpret_cast<const double2*>(oth + 2 * LCS * p + ly);
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(oth + 2 * LCS * p + lz) = nr[p];
     __syncthreads();
     double ux[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) ux[k] = su[LCS * k + lx];
-    double2 uy[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) uy[p] = *reinterpret_cast<const double2*>(su + 2 * LCS * p + ly);
+    for (int k = 0; k < NC; ++k) ux[k] = cur[LCS * k + lx];
 
-    // x direction, one cell per product
 #pragma unroll
     for (int k = 0; k < NC; ++k) {
       if (k < nvalid) {
@@ -201,7 +216,14 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
       }
     }
     __syncthreads();
-    // y direction on pairs, added onto the x results
+    const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
+    const double Ky = vy != 0 ? a.Km[1][vy][ai] : Ky_int;
+    double2 uy[2], yr[2], uz[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      uy[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + ly);
+      yr[p] = *reinterpret_cast<const double2*>(oth + 2 * LCS * p + ly);
+    }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (2 * p < nvalid) {
@@ -212,8 +234,11 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
       }
     }
     __syncthreads();
-    // z direction on pairs, the sum, the tensor weight, the store
     double* __restrict__ yc = y + (row + ex0) * 64;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      uz[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + lz);
+    }
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (2 * p < nvalid) {
@@ -227,14 +252,14 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
       }
     }
   }
-  if (DOT) {  // butterfly over the 64 lanes, then lane 0 writes
+  if (DOT) {
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) pq += __shfl_xor(pq, m, 64);
     if (lane == 0) partial[blockIdx.x] = pq;
   }
 }
 
-// The apply, with a register budget for five wavefronts per SIMD (94 VGPRs,
+// The apply, with a register budget for five wavefronts per SIMD (93 VGPRs,
 // the matrix-core results in architectural VGPRs), and the conjugate-gradient
 // variant with the fused p.Ap.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
@@ -266,16 +291,25 @@ bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa) {
 hipError_t mfma_setup(dg_mesh& M) {
   if (M.p != 4) return hipSuccess;
   const int nx = M.desc.nx, ny = M.desc.ny, nz = M.desc.nz;
-  constexpr int CW = NC * NH;  // cells per wavefront along x
-  const int nc = (nx + CW - 1) / CW;
-  const int64_t W = (int64_t)nc * ny * nz;
+  const int nc = (nx + NC - 1) / NC;
+  // Rows per wavefront: the most, up to NYMAX, that still leave at least 4096
+  // wavefronts (16 per CU), else one. Longer marches save more loads but
+  // fewer, longer wavefronts fill the chip less evenly.
+  int rows = 1;
+  for (int r = NYMAX; r > 1; r /= 2)
+    if ((int64_t)nc * ((ny + r - 1) / r) * nz >= 4096) {
+      rows = r;
+      break;
+    }
+  const int nyb = (ny + rows - 1) / rows;
+  const int64_t W = (int64_t)nc * nyb * nz;
   if (W > 0x7fffffff / 2) return hipErrorInvalidValue;
   // One region of the mesh per XCD: the split (rx, ry, rz), rx ry rz = 8, that
   // reads the fewest cells across region boundaries (each XCD has its own
   // L2, so a neighbour cell of another region is fetched again).
   int best[3] = {1, 1, 8};
   double best_cost = -1;
-  const int ext[3] = {nc, ny, nz};
+  const int ext[3] = {nc, nyb, nz};
   // The y direction is not split: the sweep runs along y, and its front (the
   // region's x-z cross-section) is the same for every (rx, rz).
   for (int rx = 1; rx <= 8; rx *= 2)
@@ -303,14 +337,15 @@ hipError_t mfma_setup(dg_mesh& M) {
     for (int gy = 0; gy < best[1]; ++gy)
       for (int gx = 0; gx < best[0]; ++gx) {
         const int c0 = bound(nc, best[0], gx), c1 = bound(nc, best[0], gx + 1);
-        const int y0 = bound(ny, best[1], gy), y1 = bound(ny, best[1], gy + 1);
+        const int y0 = bound(nyb, best[1], gy), y1 = bound(nyb, best[1], gy + 1);
         const int z0 = bound(nz, best[2], gz), z1 = bound(nz, best[2], gz + 1);
         // inside a region: y outermost, then z, then the x chunks
         for (int yy = y0; yy < y1; ++yy)
           for (int zz = z0; zz < z1; ++zz)
             for (int cc = c0; cc < c1; ++cc) {
-              order[2 * t] = (uint32_t)(cc * CW) | ((uint32_t)yy << 16);
-              order[2 * t + 1] = (uint32_t)zz;
+              const int ey0 = yy * rows;
+              order[2 * t] = (uint32_t)(cc * NC) | ((uint32_t)ey0 << 16);
+              order[2 * t + 1] = (uint32_t)zz | ((uint32_t)std::min(rows, ny - ey0) << 16);
               ++t;
             }
       }

@@ -133,6 +133,21 @@ def test_q3_64cube_full_vector(gpu_lib):
     assert relerr(y, ref) < TOL64
 
 
+@pytest.mark.parametrize("shape,mask", [((13, 71, 45), 0x2D), ((6, 130, 96), 0x17), ((10, 37, 512), 0x3F)])
+def test_q3_row_march_ragged(gpu_lib, shape, mask):
+    """Q3 meshes large enough that each wavefront of the matrix-core apply
+    marches along y over several rows (2, 4 and 16 rows per wavefront for
+    these shapes), with a shorter last march in every column, a ragged last
+    x chunk and natural sides, against the oracle's deduplicated BSR."""
+    dg = gpu_lib
+    print(f"case: Q3 row march {shape} mask={mask:#x}", flush=True)
+    nx, ny, nz = shape
+    x = workloads.uniform(nx * ny * nz * 64, 6100 + ny)
+    y = gpu_apply(dg, dg.make_desc(nx, ny, nz, k=3, dirichlet_mask=mask), x)
+    ref = ScalarDG(Problem(nx, ny, nz, k=3, mask=mask)).assemble("dedup").matvec(x)
+    assert relerr(y, ref) < TOL64
+
+
 def test_q5_40cube_full_vector(gpu_lib):
     """The Q5 40^3 solve workload (13.8M DOFs) at full size, FP64 (line-operator
     kernel) and FP32 (sum-factorized kernel), against the oracle's deduplicated BSR."""
