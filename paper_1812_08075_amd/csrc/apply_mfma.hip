@@ -173,8 +173,8 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
     const bool hy0 = ey > 0, hy1 = ey < ny - 1;
     const size_t row = row0 + (size_t)s * nx;
     const double* __restrict__ xc = x + (row + ex0) * 64;
-    double* __restrict__ cur = su + (s & 1) * (NC * LCS);
-    double* __restrict__ oth = su + ((s + 1) & 1) * (NC * LCS);
+    double* cur = su + (s & 1) * (NC * LCS);  // row y
+    double* oth = su + ((s + 1) & 1) * (NC * LCS);  // row y - 1, then row y + 1
 
     double2 nr[2], zl[2], zr[2];
 #pragma unroll
