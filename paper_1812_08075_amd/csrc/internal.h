@@ -222,6 +222,11 @@ hipError_t scalar_params_upload(dg_mesh& M);
 // Matrix-core apply of the p = 4, FP64, kappa = 1 operator (variant SP_APPLY or SP_APPLY_T).
 bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa);
 hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, double* partial, hipStream_t s);
+// The same operator on FP32 vectors, computed in FP64 on the matrix cores (the
+// FP64 kernel's result for the FP32 input, rounded to FP32).
+bool mfma_apply_f32_supported(const dg_mesh& M, int prec, bool kappa);
+hipError_t mfma_apply_f32(const dg_mesh& M, int variant, const float* x, float* y, double* partial,
+                          hipStream_t s);
 // Builds and uploads the wavefront table of the matrix-core apply (M.d_waves).
 hipError_t mfma_setup(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);

@@ -1100,13 +1100,15 @@ hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, cons
   const int v = transpose ? SP_APPLY_T : SP_APPLY;
   if (mfma_apply_supported(M, prec, kappa != nullptr))
     return mfma_apply(M, v, (const double*)x, (double*)y, partial, s);
+  if (mfma_apply_f32_supported(M, prec, kappa != nullptr))
+    return mfma_apply_f32(M, v, (const float*)x, (float*)y, partial, s);
   if (prec == DG_F64)
     return dispatch_apply<double>(M, v, (const double*)x, (double*)y, (const double*)kappa, partial, s);
   return dispatch_apply<float>(M, v, (const float*)x, (float*)y, (const float*)kappa, partial, s);
 }
 
 int64_t scalar_apply_blocks(const dg_mesh& M, int prec, bool kappa) {
-  if (mfma_apply_supported(M, prec, kappa)) return M.nwaves;
+  if (mfma_apply_supported(M, prec, kappa) || mfma_apply_f32_supported(M, prec, kappa)) return M.nwaves;
   return grid_of(M.pd[SP_APPLY]);
 }
 

@@ -94,6 +94,27 @@ def test_fp32_apply_error(gpu_lib, k):
     assert err < TOL32
 
 
+@pytest.mark.parametrize("shape,mask,theta", [((9, 7, 5), 0x3F, -1.0), ((13, 10, 6), 0x2D, 1.0),
+                                              ((13, 71, 45), 0x2D, -1.0), ((10, 37, 512), 0x17, -1.0)])
+def test_q3_fp32_is_rounded_fp64(gpu_lib, shape, mask, theta):
+    """The Q3 FP32 apply computes in FP64 on the matrix cores with the FP64
+    kernel's tables and order of operations: its output is, bit for bit, the
+    FP64 apply of the FP32 input rounded once to FP32 (ragged chunks, marches
+    of 1, 2 and 16 rows, natural sides, the non-symmetric variant)."""
+    dg = gpu_lib
+    print(f"case: Q3 FP32 vs rounded FP64 {shape} mask={mask:#x} theta={theta}", flush=True)
+    nx, ny, nz = shape
+    mesh = dg.Mesh(dg.make_desc(nx, ny, nz, k=3, dirichlet_mask=mask, theta=theta))
+    x32 = torch.from_numpy(workloads.uniform(mesh.ndofs, 6200 + nx)).to("cuda", torch.float32)
+    y32 = mesh.apply(x32)
+    y64 = mesh.apply(x32.double())
+    a32, _ = mesh.apply_adjoint(x32, want_dkappa=False)  # the transposed operator
+    a64, _ = mesh.apply_adjoint(x32.double(), want_dkappa=False)
+    torch.cuda.synchronize()
+    assert torch.equal(y32, y64.float())
+    assert torch.equal(a32, a64.float())
+
+
 @pytest.mark.parametrize("face_one", [False, True])
 @pytest.mark.parametrize("theta", [-1.0, 1.0])
 def test_kappa_per_point(gpu_lib, face_one, theta):

@@ -19,12 +19,13 @@ def setup(dg, w, n):
     return mesh, b
 
 
+@pytest.mark.parametrize("wid", [5, 2])  # Q5 (line kernels), Q3 (matrix-core kernels, FP64 and FP32)
 @pytest.mark.parametrize("mode", [0, 1, 2])
-def test_solve_matches_direct_solve(gpu_lib, mode):
+def test_solve_matches_direct_solve(gpu_lib, mode, wid):
     dg = gpu_lib
-    w = workloads.WORKLOADS[5]
+    w = workloads.WORKLOADS[wid]
     n = 4
-    print(f"case: solve mode {mode} Q5 {n}^3", flush=True)
+    print(f"case: solve mode {mode} {w.name} {n}^3", flush=True)
     mesh, b = setup(dg, w, n)
     x = torch.zeros_like(b)
     inner = 0.1 if mode == 2 else 1e-5
