@@ -134,7 +134,10 @@ dg_status dg_mesh_info(const dg_mesh* mesh, dg_mesh_info_t* out);
  * (Algorithm 1 for the cell integrals; facet integrals with the normal
  * direction contracted first, Section 2.2). kappa: device pointer, nqp values,
  * required iff kappa_mode == DG_KAPPA_QP, else ignored (may be NULL).
- * Each output entry is written exactly once; results are bitwise reproducible. */
+ * Each output entry is written exactly once; results are bitwise reproducible.
+ * DG_F32: the vectors are float. For k = 3 with kappa_mode DG_KAPPA_ONE the
+ * products run in FP64 (y is the FP64 result for the float x, rounded once to
+ * float); otherwise the arithmetic is FP32 on tables rounded once from FP64. */
 dg_status dg_apply(const dg_mesh* mesh, int precision, const void* x, void* y,
                    const void* kappa, void* stream);
 
