@@ -5,7 +5,10 @@ Argument marshalling only: every step of the operator runs in the HIP
 kernels of libdg.so. The functions mirror include/dg.h one to one
 (dg_mesh_create, dg_apply, dg_apply_adjoint, dg_solve, ...). Vectors are
 torch tensors on the GPU; the current torch stream is passed to the library.
-There is no CPU fallback: importing fails when the library is missing.
+Every tensor is checked (device, dtype, contiguity, 16-byte alignment,
+length) before its pointer is handed over, since the library only sees
+pointers. There is no CPU fallback: the library is loaded on first use
+(`lib`), and that fails loudly when libdg.so is missing.
 """
 from __future__ import annotations
 
@@ -68,6 +71,7 @@ EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mes
 
 
 def _load():
+    """Opens libdg.so and declares the argument types of every entry point."""
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                           "(python -m paper_1812_08075_amd.build); there is no CPU fallback")
@@ -93,7 +97,22 @@ def _load():
     return lib
 
 
-lib = _load()
+_LIB = None
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        _LIB = _load()
+    return _LIB
+
+
+def __getattr__(name):
+    # `lib` is resolved on first access, so that importing the package (for
+    # instance to build the library) never loads a missing or stale libdg.so
+    if name == "lib":
+        return _lib()
+    raise AttributeError(name)
 
 
 class DGError(RuntimeError):
@@ -104,18 +123,60 @@ class DGError(RuntimeError):
 
 def _check(status: int, allow=()) -> int:
     if status != DG_OK and status not in allow:
-        raise DGError(status, lib.dg_last_error().decode())
+        raise DGError(status, _lib().dg_last_error().decode())
     return status
-
-
-def _ptr(t):
-    return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
 def _stream(stream):
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+# sizes of every mesh handle this binding created (for the tensor checks)
+_SIZES = {}
+
+
+def _sizes(mesh):
+    key = mesh.value if isinstance(mesh, ctypes.c_void_p) else int(mesh)
+    sz = _SIZES.get(key)
+    if sz is None:
+        info = dg_mesh_info(mesh)
+        sz = _SIZES[key] = (int(info.ndofs), int(info.nqp))
+    return sz
+
+
+def _vec(t, n, prec, name, optional=False):
+    """Pointer of a device tensor after checking what the library cannot: a
+    GPU tensor of the precision's dtype, contiguous, 16-byte aligned, n values."""
+    if t is None:
+        if optional:
+            return None
+        raise ValueError(f"{name} is required")
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    want = _DTYPE.get(prec)
+    if want is None:
+        raise ValueError(f"precision must be DG_F64 or DG_F32, got {prec}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on the GPU (got {t.device})")
+    if t.dtype != want:
+        raise ValueError(f"{name} must be {want} for this precision (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must hold {n} values (got {t.numel()})")
+    if t.data_ptr() % 16:
+        raise ValueError(f"{name} must be 16-byte aligned")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _prec_of(t):
+    if t.dtype == torch.float64:
+        return DG_F64
+    if t.dtype == torch.float32:
+        return DG_F32
+    raise ValueError(f"vectors must be float64 or float32 (got {t.dtype})")
 
 
 def make_desc(nx, ny=None, nz=None, k=3, m=0, problem=DG_PROBLEM_DIFFREAC, c=1.0, alpha=3.0, theta=-1.0,
@@ -144,56 +205,71 @@ def desc_from_workload(w, n=None, theta=None):
 
 
 def dg_mesh_desc_validate(desc) -> int:
-    return lib.dg_mesh_desc_validate(ctypes.byref(desc))
+    return _lib().dg_mesh_desc_validate(ctypes.byref(desc))
 
 
 def dg_mesh_create(desc, stream=None):
     h = ctypes.c_void_p()
-    _check(lib.dg_mesh_create(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+    _check(_lib().dg_mesh_create(ctypes.byref(desc), _stream(stream), ctypes.byref(h)))
+    _SIZES.pop(h.value, None)
     return h
 
 
 def dg_mesh_destroy(mesh):
-    _check(lib.dg_mesh_destroy(mesh))
+    key = mesh.value if isinstance(mesh, ctypes.c_void_p) else mesh
+    _SIZES.pop(key, None)
+    _check(_lib().dg_mesh_destroy(mesh))
 
 
 def dg_mesh_info(mesh) -> dg_mesh_info_t:
     out = dg_mesh_info_t()
-    _check(lib.dg_mesh_info(mesh, ctypes.byref(out)))
+    _check(_lib().dg_mesh_info(mesh, ctypes.byref(out)))
     return out
 
 
 def dg_apply(mesh, precision, x, y, kappa=None, stream=None):
-    _check(lib.dg_apply(mesh, precision, _ptr(x), _ptr(y), _ptr(kappa), _stream(stream)))
+    n, nq = _sizes(mesh)
+    _check(_lib().dg_apply(mesh, precision, _vec(x, n, precision, "x"), _vec(y, n, precision, "y"),
+                           _vec(kappa, nq, precision, "kappa", optional=True), _stream(stream)))
 
 
 def dg_apply_adjoint(mesh, precision, g, u, kappa, ATg, dkappa=None, stream=None):
-    _check(lib.dg_apply_adjoint(mesh, precision, _ptr(g), _ptr(u), _ptr(kappa), _ptr(ATg), _ptr(dkappa),
-                                _stream(stream)))
+    n, nq = _sizes(mesh)
+    _check(_lib().dg_apply_adjoint(mesh, precision, _vec(g, n, precision, "g"),
+                                   _vec(u, n, precision, "u", optional=True),
+                                   _vec(kappa, nq, precision, "kappa", optional=True),
+                                   _vec(ATg, n, precision, "ATg"),
+                                   _vec(dkappa, nq, precision, "dkappa", optional=True), _stream(stream)))
 
 
 def dg_precond_apply(mesh, precision, r, z, stream=None):
-    _check(lib.dg_precond_apply(mesh, precision, _ptr(r), _ptr(z), _stream(stream)))
+    n, _ = _sizes(mesh)
+    _check(_lib().dg_precond_apply(mesh, precision, _vec(r, n, precision, "r"), _vec(z, n, precision, "z"),
+                                   _stream(stream)))
 
 
 def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=100000, max_outer=50,
              check_every=10, precond=DG_PRECOND_NONE, stream=None):
+    n, nq = _sizes(mesh)
     params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every, precond)
     info = dg_solve_info()
-    st = _check(lib.dg_solve(mesh, mode, _ptr(b), _ptr(x), _ptr(kappa), ctypes.byref(params),
-                             ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))
+    st = _check(_lib().dg_solve(mesh, mode, _vec(b, n, DG_F64, "b"), _vec(x, n, DG_F64, "x"),
+                                _vec(kappa, nq, DG_F64, "kappa", optional=True), ctypes.byref(params),
+                                ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))
     return st, info
 
 
 def dg_mesh_qpoints(mesh) -> np.ndarray:
     info = dg_mesh_info(mesh)
     out = np.empty((info.nqp, 3), dtype=np.float64)
-    _check(lib.dg_mesh_qpoints(mesh, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    _check(_lib().dg_mesh_qpoints(mesh, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
     return out
 
 
 def dg_load_vector(mesh, precision, fq, b, stream=None):
-    _check(lib.dg_load_vector(mesh, precision, _ptr(fq), _ptr(b), _stream(stream)))
+    n, nq = _sizes(mesh)
+    _check(_lib().dg_load_vector(mesh, precision, _vec(fq, nq, precision, "fq"), _vec(b, n, precision, "b"),
+                                 _stream(stream)))
 
 
 class Mesh:
@@ -206,8 +282,9 @@ class Mesh:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and h.value and lib is not None:
-            lib.dg_mesh_destroy(h)
+        if h is not None and h.value and _LIB is not None:
+            _SIZES.pop(h.value, None)
+            _LIB.dg_mesh_destroy(h)
             self.handle = None
 
     @property
@@ -215,13 +292,13 @@ class Mesh:
         return int(self.info.ndofs)
 
     def apply(self, x, kappa=None, out=None):
-        prec = DG_F64 if x.dtype == torch.float64 else DG_F32
+        prec = _prec_of(x)
         y = torch.empty_like(x) if out is None else out
         dg_apply(self.handle, prec, x, y, kappa)
         return y
 
     def apply_adjoint(self, g, u=None, kappa=None, want_dkappa=True):
-        prec = DG_F64 if g.dtype == torch.float64 else DG_F32
+        prec = _prec_of(g)
         ATg = torch.empty_like(g)
         dk = torch.empty(int(self.info.nqp), dtype=g.dtype, device=g.device) if want_dkappa else None
         dg_apply_adjoint(self.handle, prec, g, u, kappa, ATg, dk)

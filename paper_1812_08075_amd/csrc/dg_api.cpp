@@ -4,6 +4,8 @@
 #include <cmath>
 #include <cstring>
 #include <exception>
+#include <initializer_list>
+#include <utility>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -301,9 +303,20 @@ bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-void check_vec(const void* p, const char* name, size_t align) {
+// Every vector argument must be 16-byte aligned: the kernels read and write
+// whole 16-byte groups of elements.
+constexpr size_t kVecAlign = 16;
+
+// Alignment of the pointers that are given, checked before anything else.
+void check_align(std::initializer_list<std::pair<const void*, const char*>> ps) {
+  for (const auto& pn : ps)
+    if (pn.first && (uintptr_t)pn.first % kVecAlign)
+      fail(DG_ERR_ARG, std::string(pn.second) + " is not 16-byte aligned");
+}
+
+void check_vec(const void* p, const char* name) {
   if (!p) fail(DG_ERR_ARG, std::string(name) + " is NULL");
-  if ((uintptr_t)p % align) fail(DG_ERR_ARG, std::string(name) + " is not aligned to its element size");
+  if ((uintptr_t)p % kVecAlign) fail(DG_ERR_ARG, std::string(name) + " is not 16-byte aligned");
 }
 
 hipStream_t as_stream(void* s) { return (hipStream_t)s; }
@@ -591,16 +604,17 @@ dg_status dg_mesh_info(const dg_mesh* M, dg_mesh_info_t* out) {
 
 dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, const void* kappa, void* stream) {
   return guarded([&] {
+    check_align({{x, "x"}, {y, "y"}, {kappa, "kappa"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
     check_prec(precision);
     const size_t es = elem_size(precision);
-    check_vec(x, "x", es);
-    check_vec(y, "y", es);
+    check_vec(x, "x");
+    check_vec(y, "y");
     const size_t nb = (size_t)M->ndofs * es;
     if (overlap(x, nb, y, nb)) fail(DG_ERR_ARG, "x and y overlap");
     const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
     if (kap) {
-      check_vec(kappa, "kappa", es);
+      check_vec(kappa, "kappa");
       if (overlap(kappa, (size_t)M->nqp * es, y, nb)) fail(DG_ERR_ARG, "kappa and y overlap");
     }
     if (M->desc.problem == DG_PROBLEM_STOKES) {
@@ -616,11 +630,12 @@ dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, cons
 
 dg_status dg_precond_apply(const dg_mesh* M, int precision, const void* r, void* z, void* stream) {
   return guarded([&] {
+    check_align({{r, "r"}, {z, "z"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
     check_prec(precision);
     const size_t es = elem_size(precision);
-    check_vec(r, "r", es);
-    check_vec(z, "z", es);
+    check_vec(r, "r");
+    check_vec(z, "z");
     const size_t nb = (size_t)M->ndofs * es;
     if (overlap(r, nb, z, nb)) fail(DG_ERR_ARG, "r and z overlap");
     if (!dgi::block_jacobi_supported(*M))
@@ -634,17 +649,19 @@ dg_status dg_precond_apply(const dg_mesh* M, int precision, const void* r, void*
 dg_status dg_apply_adjoint(const dg_mesh* M, int precision, const void* g, const void* u, const void* kappa,
                            void* ATg, void* dkappa, void* stream) {
   return guarded([&] {
+    check_align({{g, "g"}, {u, "u"}, {kappa, "kappa"}, {ATg, "ATg"}, {dkappa, "dkappa"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
     if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "the adjoint is built for diffusion-reaction");
     check_prec(precision);
     const size_t es = elem_size(precision);
-    check_vec(g, "g", es);
-    check_vec(ATg, "ATg", es);
+    check_vec(g, "g");
+    check_vec(ATg, "ATg");
     const size_t nb = (size_t)M->ndofs * es, nk = (size_t)M->nqp * es;
     const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
-    if (kap) check_vec(kappa, "kappa", es);
+    if (kap) check_vec(kappa, "kappa");
     if (dkappa) {
-      check_vec(u, "u", es);
+      check_vec(dkappa, "dkappa");
+      check_vec(u, "u");
       if (overlap(dkappa, nk, g, nb) || overlap(dkappa, nk, u, nb) || overlap(dkappa, nk, ATg, nb) ||
           (kap && overlap(dkappa, nk, kappa, nk)))
         fail(DG_ERR_ARG, "dkappa overlaps another argument");
@@ -689,12 +706,13 @@ dg_status dg_mesh_qpoints(const dg_mesh* M, double* xyz) {
 
 dg_status dg_load_vector(const dg_mesh* M, int precision, const void* fq, void* b, void* stream) {
   return guarded([&] {
+    check_align({{fq, "fq"}, {b, "b"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
     if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "load vectors are built for diffusion-reaction");
     check_prec(precision);
     const size_t es = elem_size(precision);
-    check_vec(fq, "fq", es);
-    check_vec(b, "b", es);
+    check_vec(fq, "fq");
+    check_vec(b, "b");
     if (overlap(fq, (size_t)M->nqp * es, b, (size_t)M->ndofs * es)) fail(DG_ERR_ARG, "fq and b overlap");
     hip_check(dgi::scalar_load(*M, precision, fq, b, as_stream(stream)), "load vector launch");
     return DG_OK;

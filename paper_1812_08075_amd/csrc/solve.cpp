@@ -348,6 +348,10 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
 extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa,
                               const dg_solve_params* prm, dg_solve_info* info, void* stream) {
   try {
+    if (((uintptr_t)b | (uintptr_t)x | (uintptr_t)kappa) % 16) {
+      dg_set_error("b, x and kappa must be 16-byte aligned");
+      return DG_ERR_ARG;
+    }
     if (!M || !b || !x || !prm || !info) {
       dg_set_error("mesh, b, x, params and info must not be NULL");
       return DG_ERR_ARG;
@@ -378,10 +382,6 @@ extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, doubl
       return DG_ERR_ARG;
     }
     const size_t nb = sizeof(double) * (size_t)M->ndofs;
-    if (((uintptr_t)b | (uintptr_t)x) % sizeof(double)) {
-      dg_set_error("b and x must be aligned to 8 bytes");
-      return DG_ERR_ARG;
-    }
     if (overlap(b, nb, x, nb) || (kap && overlap(kappa, sizeof(double) * (size_t)M->nqp, x, nb))) {
       dg_set_error("x overlaps b or kappa");
       return DG_ERR_ARG;

@@ -207,3 +207,28 @@ def test_load_vector(gpu_lib):
     op = ScalarDG(problem_from_workload(w))
     ref = op.load_vector(lambda x: workloads.sin_forcing(x, w.c))
     assert relerr(b.cpu().numpy(), ref) < 1e-13
+
+
+def test_binding_rejects_bad_device_tensors(gpu_lib):
+    """dtype, contiguity, length and alignment of device tensors are checked by
+    the binding before any pointer reaches the library."""
+    dg = gpu_lib
+    print("case: binding tensor checks", flush=True)
+    mesh = dg.Mesh(dg.make_desc(2, 2, 2, k=2))
+    n = mesh.ndofs
+    x = torch.zeros(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    bad = [
+        (torch.zeros(n, dtype=torch.float16, device="cuda"), "float64"),
+        (torch.zeros(2 * n, dtype=torch.float64, device="cuda")[::2], "contiguous"),
+        (torch.zeros(n + 1, dtype=torch.float64, device="cuda"), "hold"),
+        (torch.zeros(n + 1, dtype=torch.float64, device="cuda")[1:], "aligned"),
+        (torch.zeros(n, dtype=torch.float32, device="cuda"), "float64"),
+    ]
+    for t, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            dg.dg_apply(mesh.handle, dg.DG_F64, t, y)
+    with pytest.raises(ValueError, match="float64 or float32"):
+        mesh.apply(torch.zeros(n, dtype=torch.int32, device="cuda"))
+    dg.dg_apply(mesh.handle, dg.DG_F64, x, y)
+    torch.cuda.synchronize()

@@ -63,7 +63,7 @@ def test_closed_form_kronecker_blocks(k):
     op = ScalarDG(pr)
     vol = c * h ** 3 * kr(M, M, M) + h * (kr(K, M, M) + kr(M, K, M) + kr(M, M, K))
     assert np.max(np.abs(op.volume_block(0) - vol)) < 1e-13 * np.max(np.abs(vol))
-    gam = pr.penalty_coef(k) / h
+    gam = 3.0 * k * (k + 1) / h  # alpha k(k+1) |F| / |T| with alpha = 3 on a cube of side h
     th = pr.theta
     # boundary face x = 0 of cell 0: outward normal -e_x, d/dn = -(1/h) d/dxi
     N1 = (-np.outer(e[0], -de[0] / h) + th * np.outer(-de[0] / h, e[0]) + gam * np.outer(e[0], e[0]))
@@ -256,3 +256,98 @@ def test_kappa_gradient_volume_closed_form_when_faces_use_one():
     h3 = (1.0 / n) ** 3
     ref = np.tile(op.prob.cell_w * h3, (n ** 3, 1))
     assert np.max(np.abs(op.kappa_gradient(ux, ux) - ref)) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# kappa per volume quadrature point: layout and face traces; the paper's penalty
+# ---------------------------------------------------------------------------
+def _layout_points(nx, ny, nz, m):
+    """Physical volume points in the library's kappa layout, written out from its
+    definition (cell e = ex + nx (ey + ny ez), point q0 + m (q1 + m q2), nodes of
+    numpy's Gauss-Legendre rule mapped to [0, 1])."""
+    t, _ = np.polynomial.legendre.leggauss(m)
+    xi = (t + 1.0) / 2.0
+    pts = []
+    for ez in range(nz):
+        for ey in range(ny):
+            for ex in range(nx):
+                for q2 in range(m):
+                    for q1 in range(m):
+                        for q0 in range(m):
+                            pts.append(((ex + xi[q0]) / nx, (ey + xi[q1]) / ny, (ez + xi[q2]) / nz))
+    return np.array(pts)
+
+
+def _kappa_linear(X):
+    return 1.0 + X[:, 0] + 2.0 * X[:, 1] + 3.0 * X[:, 2]
+
+
+@pytest.mark.parametrize("theta", [-1.0, 1.0])
+def test_kappa_per_point_layout_and_face_trace(theta):
+    """kappa(x) = 1 + x + 2y + 3z sampled in the layout above and passed per point
+    gives the same matrix as the full-tensor path with K = kappa(x) I evaluated
+    directly at every volume and face point (eq. diffreac_weak): the function is
+    not symmetric in x, y, z, so a permuted point layout or cell order fails, and
+    it has degree 1 per direction, so the face-trace interpolant of the point
+    values is exact. Mixed Dirichlet / natural sides, a non-cubic mesh."""
+    nx, ny, nz, k, mask = 3, 2, 2, 2, 0x2B
+    kap = _kappa_linear(_layout_points(nx, ny, nz, k + 1))
+    K = lambda X: _kappa_linear(X)[:, None, None] * np.eye(3)[None]
+    A1 = ScalarDG(Problem(nx, ny, nz, k=k, theta=theta, mask=mask, kappa=kap)).assemble("explicit").to_dense()
+    A2 = ScalarDG(Problem(nx, ny, nz, k=k, theta=theta, mask=mask, kappa_tensor=K)).assemble("explicit").to_dense()
+    assert np.max(np.abs(A1 - A2)) <= 1e-13 * np.max(np.abs(A2))
+    # the check has teeth: the same values with the point axes q0 and q2 swapped differ
+    m = k + 1
+    swapped = kap.reshape(-1, m, m, m).transpose(0, 3, 2, 1).reshape(-1)
+    A3 = ScalarDG(Problem(nx, ny, nz, k=k, theta=theta, mask=mask, kappa=swapped)).assemble("explicit").to_dense()
+    assert np.max(np.abs(A3 - A2)) > 1e-3 * np.max(np.abs(A2))
+
+
+def _lagrange_at(nodes, s):
+    return np.array([np.prod([(s - xi) / (xj - xi) for i, xi in enumerate(nodes) if i != j])
+                     for j, xj in enumerate(nodes)])
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_paper_penalty_form(k):
+    """penalty_form = 1 is the paper's gamma_F = alpha k(k+d-1)|F|/min|T| (Section 5.2),
+    3k(k+2)/h on cubes of side h, against 3k(k+1)/h for penalty_form = 0: the two
+    matrices differ by 3k/h times sum_F ([u], [v])_F over interior and Dirichlet
+    faces, written out here with Kronecker products of 1D factors (numpy nodes and
+    weights, Lagrange values at 0 and 1 by the product formula)."""
+    n, p = 2, k + 1
+    h = 1.0 / n
+    t, wt = np.polynomial.legendre.leggauss(p)
+    nodes, w = (t + 1.0) / 2.0, wt / 2.0
+    e = [_lagrange_at(nodes, 0.0), _lagrange_at(nodes, 1.0)]
+    Mt = h * np.diag(w)  # tangential 1D mass of the collocated basis
+    kr = lambda a, b, c: np.kron(c, np.kron(b, a))  # a acts on x (fastest)
+
+    def face(d, N1):
+        f = [Mt, Mt, Mt]
+        f[d] = N1
+        return kr(*f)
+
+    N = p ** 3
+    S = np.zeros((n ** 3 * N, n ** 3 * N))
+    cell = lambda c: c[0] + n * (c[1] + n * c[2])
+    for ez in range(n):
+        for ey in range(n):
+            for ex in range(n):
+                c = (ex, ey, ez)
+                a = cell(c)
+                for d in range(3):
+                    for s in range(2):
+                        nb = list(c)
+                        nb[d] += 1 if s else -1
+                        if 0 <= nb[d] < n:
+                            b = cell(nb)
+                            # ([u],[v]) seen from cell a: own trace at side s, neighbour's at side 1-s
+                            S[a * N:(a + 1) * N, a * N:(a + 1) * N] += face(d, np.outer(e[s], e[s]))
+                            S[a * N:(a + 1) * N, b * N:(b + 1) * N] -= face(d, np.outer(e[s], e[1 - s]))
+                        else:
+                            S[a * N:(a + 1) * N, a * N:(a + 1) * N] += face(d, np.outer(e[s], e[s]))
+    A0 = ScalarDG(Problem(n, n, n, k=k, penalty_form=0)).assemble("explicit").to_dense()
+    A1 = ScalarDG(Problem(n, n, n, k=k, penalty_form=1)).assemble("explicit").to_dense()
+    ref = (3.0 * k * (k + 2) / h - 3.0 * k * (k + 1) / h) * S
+    assert np.max(np.abs((A1 - A0) - ref)) <= 1e-13 * np.max(np.abs(A1))
