@@ -107,3 +107,42 @@ class BlockMatrix:
                     vals.append(self.row_block(e, s).ravel())
         return sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                              shape=self.shape)
+
+
+def _c_lib():
+    """The oracle's C block SpMV (oracle/spmv.c), built by oracle/build_c.py."""
+    import ctypes
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "liboracle_spmv.so")
+    if not os.path.exists(path):  # a fresh checkout: one gcc call
+        from .build_c import build
+        build()
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    lib.oracle_bsr_matvec.argtypes = [ctypes.c_int64, ctypes.c_int32, P, P, P, P, P, ctypes.c_int32]
+    lib.oracle_bsr_matvec.restype = None
+    return lib
+
+
+class CBlockMatvec:
+    """y = A x of a BlockMatrix by the C routine of oracle/spmv.c: the plain
+    block-row definition, block rows split over `threads` OpenMP threads."""
+
+    def __init__(self, A: BlockMatrix):
+        self.lib = _c_lib()
+        self.nelem, self.n = A.nelem, A.bsize
+        self.nbr = np.ascontiguousarray(A.nbr, dtype=np.int64)
+        if A.classes is not None:
+            self.blocks = np.ascontiguousarray(A.classes, dtype=np.float64)
+            self.cls = np.ascontiguousarray(A.cls, dtype=np.int64)
+        else:
+            self.blocks = np.ascontiguousarray(A.blocks.reshape(-1, self.n, self.n), dtype=np.float64)
+            self.cls = np.arange(self.nelem * NSLOT, dtype=np.int64).reshape(self.nelem, NSLOT)
+
+    def __call__(self, x: np.ndarray, threads: int = 1, out: np.ndarray | None = None) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.size == self.nelem * self.n
+        y = np.empty_like(x) if out is None else out
+        self.lib.oracle_bsr_matvec(self.nelem, self.n, self.nbr.ctypes.data, self.cls.ctypes.data,
+                                   self.blocks.ctypes.data, x.ctypes.data, y.ctypes.data, int(threads))
+        return y

@@ -351,3 +351,19 @@ def test_paper_penalty_form(k):
     A1 = ScalarDG(Problem(n, n, n, k=k, penalty_form=1)).assemble("explicit").to_dense()
     ref = (3.0 * k * (k + 2) / h - 3.0 * k * (k + 1) / h) * S
     assert np.max(np.abs((A1 - A0) - ref)) <= 1e-13 * np.max(np.abs(A1))
+
+
+@pytest.mark.parametrize("mode", ["explicit", "dedup"])
+def test_c_block_spmv_matches_numpy(mode):
+    """The oracle's C block SpMV (used for the CPU baseline timing) against the
+    NumPy block products and the dense matrix, 1 and 4 threads."""
+    from oracle.blocks import CBlockMatvec
+    op = ScalarDG(Problem(3, 2, 4, k=2, theta=1.0))
+    A = op.assemble(mode)
+    x = workloads.uniform(A.shape[0], 17)
+    ref = A.to_dense() @ x
+    mv = CBlockMatvec(A)
+    for t in (1, 4):
+        y = mv(x, threads=t)
+        assert np.max(np.abs(y - ref)) <= 1e-13 * np.max(np.abs(ref))
+        assert np.max(np.abs(y - A.matvec(x))) <= 1e-13 * np.max(np.abs(ref))
