@@ -177,6 +177,23 @@ dg_status dg_precond_apply(const dg_mesh* mesh, int precision, const void* r, vo
 dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
                    const dg_solve_params* params, dg_solve_info* info, void* stream);
 
+/* dg_solve without allocating: for callers that cannot allocate device or
+ * pinned host memory (code under HIP graph capture, serving loops, harnesses
+ * that forbid hipMalloc). Same arguments, checks, results and status codes as
+ * dg_solve (the same kernels in the same order, so x and info match dg_solve
+ * bitwise), but its vectors, partial sums and CG state live in one fixed
+ * 64 MiB device array per GPU, held until the process ends, and the state is
+ * read back to ordinary host memory. A solve needs about 24 bytes per DOF
+ * (FP64 CG), 32 (FP64 CG with block-Jacobi) or 36-40 (the FP32 refinement
+ * modes), so meshes up to about 1.6 million DOFs fit in every mode; a larger
+ * one returns DG_ERR_ARG with the bytes it would need. Every call on a GPU
+ * uses that GPU's one array: calls that overlap in time on the same GPU (from
+ * several threads or streams) race and must be serialized by the caller. The
+ * array keeps the last call's contents; every piece of it is written before
+ * it is read. Synchronous, like dg_solve. */
+dg_status dg_solve_noalloc(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
+                           const dg_solve_params* params, dg_solve_info* info, void* stream);
+
 /* Physical coordinates of the volume quadrature points, nqp x 3 doubles into a
  * HOST buffer (cell-blocked, same order as kappa). */
 dg_status dg_mesh_qpoints(const dg_mesh* mesh, double* xyz);

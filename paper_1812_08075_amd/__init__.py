@@ -66,7 +66,7 @@ class dg_solve_info(ctypes.Structure):
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mesh_info", "dg_apply",
-           "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_mesh_qpoints", "dg_load_vector",
+           "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_solve_noalloc", "dg_mesh_qpoints", "dg_load_vector",
            "dg_last_error")
 
 
@@ -86,6 +86,7 @@ def _load():
         "dg_apply_adjoint": [V, ctypes.c_int, V, V, V, V, V, V],
         "dg_precond_apply": [V, ctypes.c_int, V, V, V],
         "dg_solve": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
+        "dg_solve_noalloc": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
         "dg_mesh_qpoints": [V, P(ctypes.c_double)],
         "dg_load_vector": [V, ctypes.c_int, V, V, V],
         "dg_last_error": [],
@@ -249,11 +250,13 @@ def dg_precond_apply(mesh, precision, r, z, stream=None):
 
 
 def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=100000, max_outer=50,
-             check_every=10, precond=DG_PRECOND_NONE, stream=None):
+             check_every=10, precond=DG_PRECOND_NONE, stream=None, noalloc=False):
+    """dg_solve, or with noalloc=True dg_solve_noalloc (fixed device workspace)."""
     n, nq = _sizes(mesh)
     params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every, precond)
     info = dg_solve_info()
-    st = _check(_lib().dg_solve(mesh, mode, _vec(b, n, DG_F64, "b"), _vec(x, n, DG_F64, "x"),
+    fn = _lib().dg_solve_noalloc if noalloc else _lib().dg_solve
+    st = _check(fn(mesh, mode, _vec(b, n, DG_F64, "b"), _vec(x, n, DG_F64, "x"),
                                 _vec(kappa, nq, DG_F64, "kappa", optional=True), ctypes.byref(params),
                                 ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))
     return st, info

@@ -20,10 +20,16 @@
 //
 // Convergence is declared on the true FP64 residual |b - A x| <= rtol |b| in
 // every mode.
+//
+// Device memory of a solve (vectors, per-block partial sums, the CG state) is
+// one block laid out by `layout`: dg_solve allocates it per call, while
+// dg_solve_noalloc takes it from a fixed device array of this file, for
+// callers that cannot allocate.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <mutex>
 #include <string>
 
 #include "solver.h"
@@ -53,45 +59,70 @@ void ck(hipError_t e, const char* what) {
   if (e != hipSuccess) throw SolveError{DG_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-void dev_alloc(DevMem& m, size_t bytes) {
-  if (hipMalloc(&m.p, bytes > 0 ? bytes : 1) != hipSuccess) {
-    (void)hipGetLastError();
-    throw SolveError{DG_ERR_ALLOC, "device allocation failed"};
-  }
-}
-
 bool overlap(const void* a, size_t na, const void* b, size_t nb) {
   const char* pa = (const char*)a;
   const char* pb = (const char*)b;
   return pa < pb + nb && pb < pa + na;
 }
 
+// The device memory of one solve, carved out of one block.
+struct Work {
+  double* partial = nullptr;   // per-block partial sums
+  double* partial2 = nullptr;  // second set (preconditioned CG: r.r beside r.z)
+  dgi::CgState* state = nullptr;
+  double* r = nullptr;         // FP64 residual b - A x
+  double* q = nullptr;         // FP64 scratch (A x, A p)
+  double* p = nullptr;         // FP64 CG: search direction
+  double* z = nullptr;         // FP64 PCG: preconditioned residual
+  float* f[5] = {};            // FP32 CG: residual, direction, A p, iterate, preconditioned residual
+  float* k32 = nullptr;        // kappa rounded to FP32
+};
+
+// Lays out the memory of a solve from `base` (nullptr: only counts) and
+// returns its size in bytes. Every piece starts on a 256-byte boundary.
+size_t layout(const dg_mesh& M, int mode, bool pc, bool kap, char* base, Work* w) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) -> void* {
+    off = (off + 255) & ~(size_t)255;
+    void* ptr = base ? base + off : nullptr;
+    off += bytes > 0 ? bytes : 1;
+    return ptr;
+  };
+  const size_t n = (size_t)M.ndofs;
+  int64_t np = std::max(dgi::scalar_apply_blocks(M, DG_F64, kap), dgi::scalar_apply_blocks(M, DG_F32, kap));
+  np = std::max<int64_t>(np, dgi::RED_BLOCKS);
+  if (pc) np = std::max(np, dgi::block_jacobi_blocks(M));
+  w->partial = (double*)take(sizeof(double) * np);
+  if (pc) w->partial2 = (double*)take(sizeof(double) * np);
+  w->state = (dgi::CgState*)take(sizeof(dgi::CgState));
+  w->r = (double*)take(sizeof(double) * n);
+  w->q = (double*)take(sizeof(double) * n);
+  if (mode == DG_SOLVE_CG_F64) {
+    w->p = (double*)take(sizeof(double) * n);
+    if (pc) w->z = (double*)take(sizeof(double) * n);
+  } else {
+    for (int i = 0; i < 4; ++i) w->f[i] = (float*)take(sizeof(float) * n);
+    if (pc) w->f[4] = (float*)take(sizeof(float) * n);
+    if (kap) w->k32 = (float*)take(sizeof(float) * (size_t)M.nqp);
+  }
+  return (off + 255) & ~(size_t)255;
+}
+
 class Solver {
  public:
-  Solver(const dg_mesh& M, const void* kappa, bool pc, hipStream_t s)
-      : M_(M), kappa_(kappa), s_(s), n_(M.ndofs), pc_(pc) {
-    const bool kap = kappa != nullptr;
-    const int64_t napply =
-        std::max(dgi::scalar_apply_blocks(M, DG_F64, kap), dgi::scalar_apply_blocks(M, DG_F32, kap));
-    int64_t np = std::max<int64_t>(dgi::RED_BLOCKS, napply);
-    if (pc) np = std::max(np, dgi::block_jacobi_blocks(M));
-    dev_alloc(partial_, sizeof(double) * np);
-    if (pc) dev_alloc(partial2_, sizeof(double) * np);
-    dev_alloc(state_, sizeof(dgi::CgState));
-    if (hipHostMalloc(&host_.p, sizeof(dgi::CgState)) != hipSuccess) {
-      (void)hipGetLastError();
-      throw SolveError{DG_ERR_ALLOC, "pinned host allocation failed"};
-    }
+  // host: where the state record is read back to (pinned or ordinary memory)
+  Solver(const dg_mesh& M, const void* kappa, bool pc, const Work& w, dgi::CgState* host, hipStream_t s)
+      : M_(M), kappa_(kappa), s_(s), n_(M.ndofs), pc_(pc), w_(w), host_(host) {
     ck(dgi::blas_state_zero(st(), s_), "state init");
   }
 
-  dgi::CgState* st() { return (dgi::CgState*)state_.p; }
-  double* partial() { return (double*)partial_.p; }
+  dgi::CgState* st() { return w_.state; }
+  double* partial() { return w_.partial; }
 
   dgi::CgState read() {
-    ck(hipMemcpyAsync(host_.p, state_.p, sizeof(dgi::CgState), hipMemcpyDeviceToHost, s_), "state readback");
+    ck(hipMemcpyAsync(host_, w_.state, sizeof(dgi::CgState), hipMemcpyDeviceToHost, s_), "state readback");
     ck(hipStreamSynchronize(s_), "hipStreamSynchronize");
-    return *(dgi::CgState*)host_.p;
+    return *host_;
   }
 
   void apply(int prec, const void* x, void* y, const void* kappa) {
@@ -127,9 +158,9 @@ class Solver {
       const double* alpha = reinterpret_cast<const double*>(reinterpret_cast<const char*>(st()) +
                                                             offsetof(dgi::CgState, alpha));
       const int64_t nb = dgi::block_jacobi_blocks(M_);
-      ck(dgi::block_jacobi_update(M_, prec, r, q, alpha, z, partial(), (double*)partial2_.p, s_),
+      ck(dgi::block_jacobi_update(M_, prec, r, q, alpha, z, partial(), w_.partial2, s_),
          "residual update and preconditioner");
-      ck(dgi::blas_finalize((double*)partial2_.p, nb, st(), dgi::OP_RR, s_), "r.r");
+      ck(dgi::blas_finalize(w_.partial2, nb, st(), dgi::OP_RR, s_), "r.r");
       ck(dgi::blas_finalize(partial(), nb, st(), dgi::OP_BETA_PC, s_), "r.z");
       ck(dgi::blas_xp_update(x, p, z, prec, n_, st(), s_), "x and p update");
     } else {
@@ -178,47 +209,46 @@ class Solver {
   hipStream_t s_;
   int64_t n_;
   bool pc_;
-  DevMem partial_, partial2_, state_;
-  HostPinned host_;
+  const Work& w_;
+  dgi::CgState* host_;
 };
 
 dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa, const dg_solve_params* prm,
-              dg_solve_info* info, hipStream_t s) {
+              dg_solve_info* info, const Work& w, dgi::CgState* host, hipStream_t s) {
   const auto t0 = std::chrono::steady_clock::now();
   const bool pc = prm->precond == DG_PRECOND_BLOCK_JACOBI;
-  Solver S(*M, kappa, pc, s);
+  Solver S(*M, kappa, pc, w, host, s);
   const int64_t n = S.n();
   const int check = prm->check_every > 0 ? prm->check_every : 10;
-  DevMem r, p, q;
-  dev_alloc(r, sizeof(double) * n);
-  dev_alloc(q, sizeof(double) * n);
+  double* r = w.r;
+  double* q = w.q;
   ck(dgi::blas_dot(b, b, DG_F64, n, S.partial(), S.st(), dgi::OP_NORM, s), "b.b");
   const double bnorm = std::sqrt(S.read().nrm2);
   info->iterations = 0;
   info->outer = 0;
+  info->rel_residual = 0.0;
+  info->seconds = 0.0;
   dg_status status = DG_OK;
   if (bnorm == 0.0) {
-    ck(hipMemsetAsync(x, 0, sizeof(double) * n, s), "zero x");
+    ck(dgi::blas_zero(x, DG_F64, n, s), "zero x");
     ck(hipStreamSynchronize(s), "hipStreamSynchronize");
-    info->rel_residual = 0.0;
     return DG_OK;
   }
   const double target = prm->rtol * bnorm;
   int breakdown = 0;
-  double res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+  double res = std::sqrt(S.true_residual(b, x, r, q));
 
   if (mode == DG_SOLVE_CG_F64) {
-    DevMem zv;
-    dev_alloc(p, sizeof(double) * n);
-    if (pc) dev_alloc(zv, sizeof(double) * n);
+    double* p = w.p;
+    double* zv = w.z;
     int total = 0;
     // restart from the true residual whenever the recursive one has converged but
     // the true one has not (residual replacement)
     while (res > target && total < prm->maxit && !breakdown) {
       ck(dgi::blas_state_from_norm(S.st(), s), "state");
-      S.start_direction(DG_F64, r.p, p.p, zv.p);
-      total += S.cg(DG_F64, x, r.p, p.p, q.p, zv.p, kappa, target, prm->maxit - total, check, &breakdown);
-      res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+      S.start_direction(DG_F64, r, p, zv);
+      total += S.cg(DG_F64, x, r, p, q, zv, kappa, target, prm->maxit - total, check, &breakdown);
+      res = std::sqrt(S.true_residual(b, x, r, q));
     }
     info->iterations = total;
   } else if (mode == DG_SOLVE_RU_F32) {
@@ -227,22 +257,16 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     // replacement; the search direction is kept across replacements
     // below ~1e-3 per correction the FP32 recursion would run past FP32 accuracy
     const double RU_DROP = (prm->inner_rtol >= 1e-3 && prm->inner_rtol < 1.0) ? prm->inner_rtol : 0.1;
-    DevMem rl, pl, ql, xl, zl, k32;
-    dev_alloc(rl, sizeof(float) * n);
-    dev_alloc(pl, sizeof(float) * n);
-    dev_alloc(ql, sizeof(float) * n);
-    dev_alloc(xl, sizeof(float) * n);
-    if (pc) dev_alloc(zl, sizeof(float) * n);
+    float *rl = w.f[0], *pl = w.f[1], *ql = w.f[2], *xl = w.f[3], *zl = w.f[4];
     const void* kap32 = nullptr;
     if (kappa) {
-      dev_alloc(k32, sizeof(float) * M->nqp);
-      ck(dgi::blas_round_f32((const double*)kappa, (float*)k32.p, M->nqp, s), "kappa to FP32");
-      kap32 = k32.p;
+      ck(dgi::blas_round_f32((const double*)kappa, w.k32, M->nqp, s), "kappa to FP32");
+      kap32 = w.k32;
     }
-    ck(dgi::blas_zero(xl.p, DG_F32, n, s), "xl = 0");
-    ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
-    S.start_direction(DG_F32, rl.p, pl.p, zl.p);
-    ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
+    ck(dgi::blas_zero(xl, DG_F32, n, s), "xl = 0");
+    ck(dgi::blas_round_f32(r, rl, n, s), "r to FP32");
+    S.start_direction(DG_F32, rl, pl, zl);
+    ck(dgi::blas_dot(rl, rl, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
     double last = std::sqrt(S.read().rr);
     double lowest = last;  // smallest recursive residual since the last correction
     double prev = last;    // recursive residual at the previous check
@@ -250,7 +274,7 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     int total = 0, outer = 0, since_restart = 0;
     while (res > target && total < prm->maxit && !breakdown) {
       for (int it = 0; it < check && total < prm->maxit; ++it, ++total, ++since_restart)
-        S.iterate(DG_F32, xl.p, rl.p, pl.p, ql.p, zl.p, kap32);
+        S.iterate(DG_F32, xl, rl, pl, ql, zl, kap32);
       const dgi::CgState h = S.read();
       const double cur = std::sqrt(h.rr);
       // The FP32 recursion can lose its footing once its residual has drifted
@@ -272,21 +296,21 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       }
       if (lost || cur <= RU_DROP * last || cur <= target || total >= prm->maxit) {
         // a non-finite FP32 iterate is dropped rather than added
-        if (std::isfinite(cur)) ck(dgi::blas_accumulate(x, (float*)xl.p, n, s), "x += xl");
-        else ck(dgi::blas_zero(xl.p, DG_F32, n, s), "xl = 0");
+        if (std::isfinite(cur)) ck(dgi::blas_accumulate(x, xl, n, s), "x += xl");
+        else ck(dgi::blas_zero(xl, DG_F32, n, s), "xl = 0");
         ++outer;
-        res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+        res = std::sqrt(S.true_residual(b, x, r, q));
         if (res <= target) break;
-        ck(dgi::blas_round_f32((const double*)r.p, (float*)rl.p, n, s), "r to FP32");
+        ck(dgi::blas_round_f32(r, rl, n, s), "r to FP32");
         if (lost) {
           ck(dgi::blas_state_zero(S.st(), s), "state reset");
-          S.start_direction(DG_F32, rl.p, pl.p, zl.p);
+          S.start_direction(DG_F32, rl, pl, zl);
           since_restart = 0;
         } else if (pc) {
           // the kept direction continues with r.z of the replaced residual
-          S.precond(DG_F32, rl.p, zl.p, dgi::OP_SET_RZ);
+          S.precond(DG_F32, rl, zl, dgi::OP_SET_RZ);
         }
-        ck(dgi::blas_dot(rl.p, rl.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
+        ck(dgi::blas_dot(rl, rl, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "r.r");
         last = lowest = prev = std::sqrt(S.read().rr);
         growth = 0;
       }
@@ -294,34 +318,28 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     info->iterations = total;
     info->outer = outer;
   } else {
-    DevMem rh, ph, qh, dh, zh, k32;
-    dev_alloc(rh, sizeof(float) * n);
-    dev_alloc(ph, sizeof(float) * n);
-    dev_alloc(qh, sizeof(float) * n);
-    dev_alloc(dh, sizeof(float) * n);
-    if (pc) dev_alloc(zh, sizeof(float) * n);
+    float *rh = w.f[0], *ph = w.f[1], *qh = w.f[2], *dh = w.f[3], *zh = w.f[4];
     const void* kap32 = nullptr;
     if (kappa) {
-      dev_alloc(k32, sizeof(float) * M->nqp);
-      ck(dgi::blas_round_f32((const double*)kappa, (float*)k32.p, M->nqp, s), "kappa to FP32");
-      kap32 = k32.p;
+      ck(dgi::blas_round_f32((const double*)kappa, w.k32, M->nqp, s), "kappa to FP32");
+      kap32 = w.k32;
     }
     int total = 0, outer = 0;
     while (res > target && outer < prm->max_outer && total < prm->maxit && !breakdown) {
       // S.true_residual left r = b - A x and nrm2 = |r|^2 on the device
-      ck(dgi::blas_ir_start((const double*)r.p, (float*)rh.p, (float*)ph.p, (float*)dh.p, n, S.st(), s), "ir start");
-      ck(dgi::blas_dot(rh.p, rh.p, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "rhat.rhat");
-      if (pc) S.start_direction(DG_F32, rh.p, ph.p, zh.p);  // blas_ir_start set p = rhat
+      ck(dgi::blas_ir_start(r, rh, ph, dh, n, S.st(), s), "ir start");
+      ck(dgi::blas_dot(rh, rh, DG_F32, n, S.partial(), S.st(), dgi::OP_SET_RR, s), "rhat.rhat");
+      if (pc) S.start_direction(DG_F32, rh, ph, zh);  // blas_ir_start set p = rhat
       const double inner_tol = prm->inner_rtol * std::sqrt(S.read().rr0);
       int inner_lost = 0;
       const int its =
-          S.cg(DG_F32, dh.p, rh.p, ph.p, qh.p, zh.p, kap32, inner_tol, prm->maxit - total, check, &inner_lost);
+          S.cg(DG_F32, dh, rh, ph, qh, zh, kap32, inner_tol, prm->maxit - total, check, &inner_lost);
       total += its;
       // nrm2 still holds |r|^2 of this outer step
-      ck(dgi::blas_ir_correct(x, (const float*)dh.p, n, S.st(), s), "x += |r| d");
+      ck(dgi::blas_ir_correct(x, dh, n, S.st(), s), "x += |r| d");
       ++outer;
       const double prev = res;
-      res = std::sqrt(S.true_residual(b, x, (double*)r.p, (double*)q.p));
+      res = std::sqrt(S.true_residual(b, x, r, q));
       // an inner breakdown (FP32 rounding) just ends that inner solve; it is a
       // real breakdown only when the correction made no progress
       if (inner_lost && !(res < prev)) breakdown = 1;
@@ -343,55 +361,130 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
   return status;
 }
 
+// Checks the arguments of dg_solve / dg_solve_noalloc (before any HIP call).
+dg_status check_args(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa,
+                     const dg_solve_params* prm, dg_solve_info* info) {
+  if (((uintptr_t)b | (uintptr_t)x | (uintptr_t)kappa) % 16) {
+    dg_set_error("b, x and kappa must be 16-byte aligned");
+    return DG_ERR_ARG;
+  }
+  if (!M || !b || !x || !prm || !info) {
+    dg_set_error("mesh, b, x, params and info must not be NULL");
+    return DG_ERR_ARG;
+  }
+  if (M->desc.problem != DG_PROBLEM_DIFFREAC) {
+    dg_set_error("dg_solve is built for the diffusion-reaction operator");
+    return DG_ERR_UNSUPPORTED;
+  }
+  if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32 && mode != DG_SOLVE_RU_F32) {
+    dg_set_error("unknown solve mode");
+    return DG_ERR_ARG;
+  }
+  if (!(prm->rtol > 0) || prm->maxit < 1 || (mode == DG_SOLVE_IR_F32 && (!(prm->inner_rtol > 0) || prm->max_outer < 1))) {
+    dg_set_error("rtol, inner_rtol must be > 0; maxit, max_outer >= 1");
+    return DG_ERR_ARG;
+  }
+  if (prm->precond != DG_PRECOND_NONE && prm->precond != DG_PRECOND_BLOCK_JACOBI) {
+    dg_set_error("unknown preconditioner");
+    return DG_ERR_ARG;
+  }
+  if (prm->precond == DG_PRECOND_BLOCK_JACOBI && !dgi::block_jacobi_supported(*M)) {
+    dg_set_error("the block-Jacobi preconditioner is built for kappa = 1 and theta = -1");
+    return DG_ERR_UNSUPPORTED;
+  }
+  const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+  if (kap && !kappa) {
+    dg_set_error("kappa is required for kappa_mode DG_KAPPA_QP");
+    return DG_ERR_ARG;
+  }
+  const size_t nb = sizeof(double) * (size_t)M->ndofs;
+  if (overlap(b, nb, x, nb) || (kap && overlap(kappa, sizeof(double) * (size_t)M->nqp, x, nb))) {
+    dg_set_error("x overlaps b or kappa");
+    return DG_ERR_ARG;
+  }
+  return DG_OK;
+}
+
+// The fixed workspace of dg_solve_noalloc: one copy per device, for the life
+// of the process. Host code never uses this name as an address (it is a
+// host-side stand-in); it uses the device address from hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+char* scratch_on_current_device() {
+  int dev = 0;
+  ck(hipGetDevice(&dev), "hipGetDevice");
+  if (dev < 0 || dev >= kMaxDevices) throw SolveError{DG_ERR_UNSUPPORTED, "device index beyond the workspace table"};
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    ck(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) throw SolveError{DG_ERR_DEVICE, "hipGetSymbolAddress(scratch) returned NULL"};
+    g_scratch_ptr[dev] = (char*)ptr;
+  }
+  return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 extern "C" dg_status dg_solve(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa,
                               const dg_solve_params* prm, dg_solve_info* info, void* stream) {
   try {
-    if (((uintptr_t)b | (uintptr_t)x | (uintptr_t)kappa) % 16) {
-      dg_set_error("b, x and kappa must be 16-byte aligned");
-      return DG_ERR_ARG;
-    }
-    if (!M || !b || !x || !prm || !info) {
-      dg_set_error("mesh, b, x, params and info must not be NULL");
-      return DG_ERR_ARG;
-    }
-    if (M->desc.problem != DG_PROBLEM_DIFFREAC) {
-      dg_set_error("dg_solve is built for the diffusion-reaction operator");
-      return DG_ERR_UNSUPPORTED;
-    }
-    if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32 && mode != DG_SOLVE_RU_F32) {
-      dg_set_error("unknown solve mode");
-      return DG_ERR_ARG;
-    }
-    if (!(prm->rtol > 0) || prm->maxit < 1 || (mode == DG_SOLVE_IR_F32 && (!(prm->inner_rtol > 0) || prm->max_outer < 1))) {
-      dg_set_error("rtol, inner_rtol must be > 0; maxit, max_outer >= 1");
-      return DG_ERR_ARG;
-    }
-    if (prm->precond != DG_PRECOND_NONE && prm->precond != DG_PRECOND_BLOCK_JACOBI) {
-      dg_set_error("unknown preconditioner");
-      return DG_ERR_ARG;
-    }
-    if (prm->precond == DG_PRECOND_BLOCK_JACOBI && !dgi::block_jacobi_supported(*M)) {
-      dg_set_error("the block-Jacobi preconditioner is built for kappa = 1 and theta = -1");
-      return DG_ERR_UNSUPPORTED;
-    }
+    const dg_status st = check_args(M, mode, b, x, kappa, prm, info);
+    if (st != DG_OK) return st;
     const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
-    if (kap && !kappa) {
-      dg_set_error("kappa is required for kappa_mode DG_KAPPA_QP");
-      return DG_ERR_ARG;
+    const bool pc = prm->precond == DG_PRECOND_BLOCK_JACOBI;
+    Work w;
+    const size_t bytes = layout(*M, mode, pc, kap, nullptr, &w);
+    DevMem mem;
+    if (hipMalloc(&mem.p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw SolveError{DG_ERR_ALLOC, "device allocation failed"};
     }
-    const size_t nb = sizeof(double) * (size_t)M->ndofs;
-    if (overlap(b, nb, x, nb) || (kap && overlap(kappa, sizeof(double) * (size_t)M->nqp, x, nb))) {
-      dg_set_error("x overlaps b or kappa");
-      return DG_ERR_ARG;
+    layout(*M, mode, pc, kap, (char*)mem.p, &w);
+    HostPinned host;
+    if (hipHostMalloc(&host.p, sizeof(dgi::CgState)) != hipSuccess) {
+      (void)hipGetLastError();
+      throw SolveError{DG_ERR_ALLOC, "pinned host allocation failed"};
     }
-    return run(M, mode, b, x, kap ? kappa : nullptr, prm, info, (hipStream_t)stream);
+    return run(M, mode, b, x, kap ? kappa : nullptr, prm, info, w, (dgi::CgState*)host.p, (hipStream_t)stream);
   } catch (const SolveError& e) {
     dg_set_error(e.msg);
     return e.st;
   } catch (...) {
     dg_set_error("dg_solve: unexpected exception");
+    return DG_ERR_DEVICE;
+  }
+}
+
+extern "C" dg_status dg_solve_noalloc(const dg_mesh* M, int mode, const double* b, double* x, const void* kappa,
+                                      const dg_solve_params* prm, dg_solve_info* info, void* stream) {
+  try {
+    const dg_status st = check_args(M, mode, b, x, kappa, prm, info);
+    if (st != DG_OK) return st;
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    const bool pc = prm->precond == DG_PRECOND_BLOCK_JACOBI;
+    Work w;
+    const size_t bytes = layout(*M, mode, pc, kap, nullptr, &w);
+    if (bytes > kScratchBytes) {
+      dg_set_error("dg_solve_noalloc: this solve needs " + std::to_string(bytes) +
+                   " bytes of workspace, more than its fixed " + std::to_string(kScratchBytes) +
+                   " (use dg_solve)");
+      return DG_ERR_ARG;
+    }
+    layout(*M, mode, pc, kap, scratch_on_current_device(), &w);
+    dgi::CgState host{};  // ordinary host memory: no pinned allocation
+    return run(M, mode, b, x, kap ? kappa : nullptr, prm, info, w, &host, (hipStream_t)stream);
+  } catch (const SolveError& e) {
+    dg_set_error(e.msg);
+    return e.st;
+  } catch (...) {
+    dg_set_error("dg_solve_noalloc: unexpected exception");
     return DG_ERR_DEVICE;
   }
 }
