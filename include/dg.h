@@ -12,7 +12,13 @@
  *                        (Section 5.2, eq. diffreac_weak), Nitsche terms on
  *                        the Dirichlet sides;
  *   DG_PROBLEM_STOKES    velocity Q_k^3 / pressure Q_{k-1} DG Stokes
- *                        (Section 5.3, eq. stokes_weak), mu = 1.
+ *                        (Section 5.3, eq. stokes_weak), mu = 1;
+ *   DG_PROBLEM_DIFFREAC_PAPER  Section 5.2's benchmark problem: the same SIPG
+ *                        form with the full tensor K(x) = x x^T + I evaluated
+ *                        at every quadrature point, reaction c (the paper
+ *                        uses 10), source f = -6 and Dirichlet data
+ *                        g(x) = |x|^2 on the Dirichlet sides; dg_apply is its
+ *                        Jacobian action, dg_residual its full residual.
  *
  * Meshes are structured nx*ny*nz hexahedra of the unit cube, cell
  * e = ex + nx*(ey + ny*ez). Each cell is the image of [0,1]^3 under the
@@ -60,7 +66,7 @@ typedef enum {
   DG_BREAKDOWN = 2          /* dg_solve met p^T A p <= 0 or a non-finite value */
 } dg_status;
 
-enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1 };
+enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1, DG_PROBLEM_DIFFREAC_PAPER = 2 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
 enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
@@ -193,6 +199,13 @@ dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, co
  * it is read. Synchronous, like dg_solve. */
 dg_status dg_solve_noalloc(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
                            const dg_solve_params* params, dg_solve_info* info, void* stream);
+
+/* r = R(u): the full algebraic residual R_i(u) = r(u_h, phi_i) of the
+ * problem, u-independent terms included (Section 2.1), for
+ * DG_PROBLEM_DIFFREAC_PAPER: eq. diffreac_weak with K = x x^T + I, f = -6 and
+ * g = |x|^2, i.e. r = A u - b with b the source and Dirichlet data terms.
+ * Other problems: DG_ERR_UNSUPPORTED. Same vector rules as dg_apply. Async. */
+dg_status dg_residual(const dg_mesh* mesh, int precision, const void* u, void* r, void* stream);
 
 /* Physical coordinates of the volume quadrature points, nqp x 3 doubles into a
  * HOST buffer (cell-blocked, same order as kappa). */

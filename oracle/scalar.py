@@ -293,14 +293,19 @@ class ScalarDG:
         """b_i = (f, phi_i) + sum over Dirichlet faces of theta (g, K grad phi_i . n)
         + gamma_F (g, phi_i): the u-independent terms of eq. diffreac_weak moved to
         the right-hand side."""
+        return self.load_rows(f, gD, range(self.prob.mesh.nelem)).reshape(-1)
+
+    def load_rows(self, f, gD, elems) -> np.ndarray:
+        """The rows of the load vector of the given cells, (len(elems), N)."""
         pr = self.prob
         mesh = pr.mesh
-        b = np.zeros((mesh.nelem, self.N))
-        for e in range(mesh.nelem):
+        elems = [int(e) for e in elems]
+        b = np.zeros((len(elems), self.N))
+        for r, e in enumerate(elems):
             J = mesh.jacobian(e, pr.cell_xi)
             wd = pr.cell_w * np.abs(np.linalg.det(J))
             x = mesh.map(e, pr.cell_xi)
-            b[e] += self.phi_c.T @ (wd * f(x))
+            b[r] += self.phi_c.T @ (wd * f(x))
             if gD is None:
                 continue
             for d in range(3):
@@ -312,8 +317,8 @@ class ScalarDG:
                         flux = -flux
                     gam = self.gamma(dA.sum(), (self.cell_volume(e),))
                     gv = gD(xf)
-                    b[e] += pr.theta * flux.T @ (dA * gv) + gam * phi.T @ (dA * gv)
-        return b.reshape(-1)
+                    b[r] += pr.theta * flux.T @ (dA * gv) + gam * phi.T @ (dA * gv)
+        return b
 
     def interpolate(self, fn) -> np.ndarray:
         """Nodal interpolant of fn (values at the mapped basis nodes)."""

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_DEVICE, DG_ERR_ALLOC = 0, -1, -2, -3, -4
 DG_NOT_CONVERGED, DG_BREAKDOWN = 1, 2
-DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES = 0, 1
+DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES, DG_PROBLEM_DIFFREAC_PAPER = 0, 1, 2
 DG_F64, DG_F32 = 0, 1
 DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
 DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
@@ -66,8 +66,8 @@ class dg_solve_info(ctypes.Structure):
 
 # every symbol include/dg.h declares
 EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mesh_info", "dg_apply",
-           "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_solve_noalloc", "dg_mesh_qpoints", "dg_load_vector",
-           "dg_last_error")
+           "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_solve_noalloc", "dg_residual", "dg_mesh_qpoints",
+           "dg_load_vector", "dg_last_error")
 
 
 def _load():
@@ -87,6 +87,7 @@ def _load():
         "dg_precond_apply": [V, ctypes.c_int, V, V, V],
         "dg_solve": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
         "dg_solve_noalloc": [V, ctypes.c_int, V, V, V, P(dg_solve_params), P(dg_solve_info), V],
+        "dg_residual": [V, ctypes.c_int, V, V, V],
         "dg_mesh_qpoints": [V, P(ctypes.c_double)],
         "dg_load_vector": [V, ctypes.c_int, V, V, V],
         "dg_last_error": [],
@@ -260,6 +261,12 @@ def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=10
                                 _vec(kappa, nq, DG_F64, "kappa", optional=True), ctypes.byref(params),
                                 ctypes.byref(info), _stream(stream)), allow=(DG_NOT_CONVERGED, DG_BREAKDOWN))
     return st, info
+
+
+def dg_residual(mesh, precision, u, r, stream=None):
+    n, _ = _sizes(mesh)
+    _check(_lib().dg_residual(mesh, precision, _vec(u, n, precision, "u"), _vec(r, n, precision, "r"),
+                              _stream(stream)))
 
 
 def dg_mesh_qpoints(mesh) -> np.ndarray:

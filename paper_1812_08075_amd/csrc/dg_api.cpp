@@ -53,7 +53,8 @@ void validate(const dg_mesh_desc* d) {
   if (!d) fail(DG_ERR_ARG, "desc is NULL");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) fail(DG_ERR_ARG, "nx, ny, nz must be >= 1");
   if (d->nx > 65535 || d->ny > 65535 || d->nz > 65535) fail(DG_ERR_ARG, "nx, ny, nz must be <= 65535");
-  if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES) fail(DG_ERR_ARG, "unknown problem");
+  if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES && d->problem != DG_PROBLEM_DIFFREAC_PAPER)
+    fail(DG_ERR_ARG, "unknown problem");
   if (d->k < 1) fail(DG_ERR_ARG, "k must be >= 1");
   if (d->m < 0) fail(DG_ERR_ARG, "m must be >= 0");
   if (!std::isfinite(d->c) || !std::isfinite(d->alpha) || !std::isfinite(d->theta))
@@ -69,8 +70,10 @@ void validate(const dg_mesh_desc* d) {
   if (d->k + 1 > dgi::PMAX) fail(DG_ERR_UNSUPPORTED, "degree k > 7 is not built");
   if (quad_points(*d) != d->k + 1)
     fail(DG_ERR_UNSUPPORTED, "only m = k + 1 (collocated Gauss-Legendre basis) is built");
-  if (d->problem == DG_PROBLEM_DIFFREAC) {
+  if (d->problem == DG_PROBLEM_DIFFREAC || d->problem == DG_PROBLEM_DIFFREAC_PAPER) {
     if (d->vertices) fail(DG_ERR_UNSUPPORTED, "diffusion-reaction runs on the regular (axis-aligned) grid only");
+    if (d->problem == DG_PROBLEM_DIFFREAC_PAPER && d->kappa_mode != DG_KAPPA_ONE)
+      fail(DG_ERR_ARG, "the paper's problem has its own coefficient tensor: kappa_mode must be DG_KAPPA_ONE");
   } else {
     if (d->k < 2) fail(DG_ERR_UNSUPPORTED, "Stokes needs k >= 2");
     if (d->kappa_mode != DG_KAPPA_ONE) fail(DG_ERR_ARG, "Stokes has no kappa");
@@ -209,7 +212,10 @@ void fill_scalar_args(const dg_mesh& M, dgi::ScalarArgs<T>& a) {
       a.e[s][j] = (T)t.e[s][j];
       a.de[s][j] = (T)t.de[s][j];
     }
-  for (int q = 0; q < p; ++q) a.w[q] = (T)t.wq[q];
+  for (int q = 0; q < p; ++q) {
+    a.w[q] = (T)t.wq[q];
+    a.xi[q] = (T)t.xq[q];
+  }
   const int n[3] = {M.desc.nx, M.desc.ny, M.desc.nz};
   double h[3];
   for (int d = 0; d < 3; ++d) h[d] = 1.0 / n[d];
@@ -523,7 +529,7 @@ dg_status dg_mesh_create(const dg_mesh_desc* desc, void* stream, dg_mesh** out) 
                 "hipDeviceGetAttribute");
       fill_scalar_args(*M, M->sd);
       fill_scalar_args(*M, M->sf);
-      if (desc->problem == DG_PROBLEM_DIFFREAC) {
+      if (desc->problem != DG_PROBLEM_STOKES) {
         if (hipMalloc(&M->d_pd, sizeof(M->pd)) != hipSuccess || hipMalloc(&M->d_pf, sizeof(M->pf)) != hipSuccess) {
           (void)hipGetLastError();
           fail(DG_ERR_ALLOC, "device allocation failed (parameter blocks)");
@@ -586,6 +592,16 @@ dg_status dg_mesh_info(const dg_mesh* M, dg_mesh_info_t* out) {
       out->bytes_apply[0] = (double)M->ndofs * (16 + (kap ? 8 : 0));
       out->bytes_apply[1] = (double)M->ndofs * (8 + (kap ? 4 : 0));
       out->bytes_adjoint = (double)M->ndofs * 40;
+    } else if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER) {
+      // per cell: three forward and three transposed contractions (12 p^4),
+      // K(x) grad u and the mass term per point (~25 p^3), and per direction
+      // and line both faces: own and neighbour traces and normal derivatives,
+      // tangential derivatives of both traces, flux, tangential test
+      // contractions and test rows (~48 p + 60 per line and direction)
+      out->flops_apply = E * (12 * p * p * p * p + 25 * p * p * p + 3 * p * p * (48 * p + 60) + p * p * p);
+      out->flops_adjoint = out->flops_apply;
+      out->bytes_apply[0] = (double)M->ndofs * 16;
+      out->bytes_apply[1] = (double)M->ndofs * 8;
     } else {
       const double kp = M->kp;
       // per cell: 3 components x 3 gradient contractions forward and back
@@ -622,6 +638,10 @@ dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, cons
       hip_check(dgi::stokes_apply(*M, (const double*)x, (double*)y, as_stream(stream)), "stokes apply launch");
       return DG_OK;
     }
+    if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER) {
+      hip_check(dgi::tensor_apply(*M, precision, x, y, false, false, as_stream(stream)), "apply launch");
+      return DG_OK;
+    }
     hip_check(dgi::scalar_apply(*M, precision, x, y, kap ? kappa : nullptr, false, as_stream(stream)),
               "apply launch");
     return DG_OK;
@@ -651,7 +671,10 @@ dg_status dg_apply_adjoint(const dg_mesh* M, int precision, const void* g, const
   return guarded([&] {
     check_align({{g, "g"}, {u, "u"}, {kappa, "kappa"}, {ATg, "ATg"}, {dkappa, "dkappa"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
-    if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "the adjoint is built for diffusion-reaction");
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC && M->desc.problem != DG_PROBLEM_DIFFREAC_PAPER)
+      fail(DG_ERR_UNSUPPORTED, "the adjoint is built for diffusion-reaction");
+    if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER && dkappa)
+      fail(DG_ERR_UNSUPPORTED, "the paper's problem has no kappa to differentiate (dkappa must be NULL)");
     check_prec(precision);
     const size_t es = elem_size(precision);
     check_vec(g, "g");
@@ -670,11 +693,31 @@ dg_status dg_apply_adjoint(const dg_mesh* M, int precision, const void* g, const
     if (overlap(ATg, nb, g, nb)) fail(DG_ERR_ARG, "ATg and g overlap");
     if (kap && overlap(ATg, nb, kappa, nk)) fail(DG_ERR_ARG, "ATg and kappa overlap");
     hipStream_t s = as_stream(stream);
+    if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER) {
+      hip_check(dgi::tensor_apply(*M, precision, g, ATg, true, false, s), "adjoint launch");
+      return DG_OK;
+    }
     if (!dkappa) {
       hip_check(dgi::scalar_apply(*M, precision, g, ATg, kap ? kappa : nullptr, true, s), "adjoint launch");
       return DG_OK;
     }
     hip_check(dgi::scalar_adjoint(*M, precision, g, u, kap ? kappa : nullptr, ATg, dkappa, s), "adjoint launch");
+    return DG_OK;
+  });
+}
+
+dg_status dg_residual(const dg_mesh* M, int precision, const void* u, void* r, void* stream) {
+  return guarded([&] {
+    check_align({{u, "u"}, {r, "r"}});
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    check_prec(precision);
+    check_vec(u, "u");
+    check_vec(r, "r");
+    const size_t nb = (size_t)M->ndofs * elem_size(precision);
+    if (overlap(u, nb, r, nb)) fail(DG_ERR_ARG, "u and r overlap");
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC_PAPER)
+      fail(DG_ERR_UNSUPPORTED, "dg_residual needs a problem with its data (DG_PROBLEM_DIFFREAC_PAPER)");
+    hip_check(dgi::tensor_apply(*M, precision, u, r, false, true, as_stream(stream)), "residual launch");
     return DG_OK;
   });
 }
@@ -708,7 +751,7 @@ dg_status dg_load_vector(const dg_mesh* M, int precision, const void* fq, void* 
   return guarded([&] {
     check_align({{fq, "fq"}, {b, "b"}});
     if (!M) fail(DG_ERR_ARG, "mesh is NULL");
-    if (M->desc.problem != DG_PROBLEM_DIFFREAC) fail(DG_ERR_UNSUPPORTED, "load vectors are built for diffusion-reaction");
+    if (M->desc.problem == DG_PROBLEM_STOKES) fail(DG_ERR_UNSUPPORTED, "load vectors are built for diffusion-reaction");
     check_prec(precision);
     const size_t es = elem_size(precision);
     check_vec(fq, "fq");

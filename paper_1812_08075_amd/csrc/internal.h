@@ -74,6 +74,7 @@ struct alignas(16) ScalarArgs {
   T e[2][PMAX];        // face trace rows
   T de[2][PMAX];       // face derivative rows (reference coordinates)
   T w[PMAX];           // quadrature weights
+  T xi[PMAX];          // nodes = quadrature points on [0, 1]
   T vs[3];             // |J| / h_d^2: volume diffusion scale of direction d
   T fs[3];             // |J| / h_d: face area element of faces normal to d
   T hinv[3];           // 1 / h_d
@@ -230,6 +231,10 @@ hipError_t mfma_apply_f32(const dg_mesh& M, int variant, const float* x, float* 
 // Builds and uploads the wavefront table of the matrix-core apply (M.d_waves).
 hipError_t mfma_setup(dg_mesh& M);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
+// Section 5.2's benchmark operator (K = x x^T + I per point): y = A x (the
+// Jacobian action), or with `residual` y = A x - b with its f and g terms.
+hipError_t tensor_apply(const dg_mesh& M, int prec, const void* x, void* y, bool transpose, bool residual,
+                        hipStream_t s);
 
 // Vector kernels of the solvers (deterministic fixed-order reductions).
 hipError_t blas_dot_partial(const void* a, const void* b, int prec, int64_t n, double* partial,

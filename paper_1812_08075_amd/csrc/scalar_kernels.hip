@@ -49,50 +49,10 @@
 //  * Also here: the adjoint (A^T g and dL/dkappa in one pass), the
 //    block-Jacobi preconditioner (each cell's diagonal block inverted by fast
 //    diagonalization) and the load vector.
-#include "internal.h"
+#include "line_common.h"
 
 namespace dgi {
 namespace {
-
-// LDS layout of one cell block: node (i0, i1, i2) at i0 + S1 i1 + S2 i2,
-// cells NP apart. Padded strides break the power-of-two bank patterns of the
-// three line directions.
-template <int P>
-struct Layout {
-  static constexpr int S1 = P, S2 = P * P, NP = P * P * P;
-};
-template <>
-struct Layout<4> {
-  static constexpr int S1 = 4, S2 = 19, NP = 76;
-};
-template <>
-struct Layout<6> {
-  static constexpr int S1 = 6, S2 = 39, NP = 244;
-};
-template <>
-struct Layout<7> {
-  static constexpr int S1 = 7, S2 = 52, NP = 369;
-};
-template <>
-struct Layout<8> {
-  static constexpr int S1 = 9, S2 = 72, NP = 576;
-};
-
-struct BlockCoord {
-  int ex0, ey, ez;  // x index of the chunk's first cell, y and z of its row
-};
-
-// Coordinates of this hardware block's chunk (table built on the host: sweep
-// order, XCD-aware renumbering).
-template <typename T>
-__device__ __forceinline__ BlockCoord block_coord(const ScalarArgs<T>& a) {
-  const uint32_t w0 = a.blocks[2 * blockIdx.x], w1 = a.blocks[2 * blockIdx.x + 1];
-  BlockCoord c;
-  c.ex0 = (int)(w0 & 0xffffu);
-  c.ey = (int)(w0 >> 16);
-  c.ez = (int)w1;
-  return c;
-}
 
 template <int P>
 struct CellsPerBlock {
@@ -104,21 +64,6 @@ template <int P>
 struct AdjCellsPerBlock {
   static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
 };
-
-// Copies the calling thread's share of its cell into the padded LDS layout:
-// the thread that owns the lines (ta, tb) of cell le moves the P nodes
-// (ta, tb, 0..P-1), one z-plane apart. Per load the lanes of a cell read one
-// contiguous plane of it.
-template <int P, typename T>
-__device__ __forceinline__ void load_cell_column(T* __restrict__ s, const T* __restrict__ g, uint32_t gbase,
-                                                 int le, int ta, int tb) {
-  constexpr int L = P * P, N = P * P * P;
-  using Ly = Layout<P>;
-  const T* __restrict__ gc = g + gbase + (le * N + ta + P * tb);
-  T* __restrict__ sc = s + le * Ly::NP + ta + Ly::S1 * tb;
-#pragma unroll
-  for (int j = 0; j < P; ++j) sc[j * Ly::S2] = gc[j * L];
-}
 
 // Volume and face work of one 1D line of one cell in direction DIR, without
 // the line's tangential quadrature weight w_a w_b, which the caller applies once.
@@ -367,53 +312,6 @@ __device__ __forceinline__ void line_work(const T* v, const T* kv, const T (*nb)
   }
 }
 
-// Reads the line of direction DIR at (ta, tb) of LDS cell block `sc`.
-template <int P, typename T, int DIR>
-__device__ __forceinline__ void lds_line(const T* __restrict__ sc, int ta, int tb, T* v) {
-  using Ly = Layout<P>;
-  const int off = DIR == 0 ? Ly::S1 * ta + Ly::S2 * tb : (DIR == 1 ? ta + Ly::S2 * tb : ta + Ly::S1 * tb);
-  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? Ly::S1 : Ly::S2);
-#pragma unroll
-  for (int j = 0; j < P; ++j) v[j] = sc[off + j * S];
-}
-
-// Reads the line of direction DIR at (ta, tb) of the global cell block at `base`.
-template <int P, typename T, int DIR>
-__device__ __forceinline__ void global_line(const T* __restrict__ g, uint32_t base, int ta, int tb, T* v) {
-  constexpr int L = P * P;
-  const T* __restrict__ gl = g + base + (DIR == 0 ? P * ta + L * tb : (DIR == 1 ? ta + L * tb : ta + P * tb));
-  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? P : L);
-#pragma unroll
-  for (int j = 0; j < P; ++j) v[j] = gl[j * S];
-}
-
-// Neighbour lines of direction DIR for both sides (x-neighbours inside the
-// chunk come from LDS, everything else from global memory / L2).
-template <int P, typename T, int DIR>
-__device__ __forceinline__ void neighbor_lines(const T* __restrict__ s, const T* __restrict__ g, uint32_t e,
-                                               int le, int nvalid, int ecd, int nd, uint32_t estride, int ta,
-                                               int tb, T (*nb)[P], bool* has) {
-  constexpr int N = P * P * P;
-  using Ly = Layout<P>;
-  has[0] = ecd > 0;
-  has[1] = ecd < nd - 1;
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    if (!has[side]) {
-#pragma unroll
-      for (int j = 0; j < P; ++j) nb[side][j] = T(0);
-      continue;
-    }
-    const int lnb = side ? le + 1 : le - 1;
-    if (DIR == 0 && lnb >= 0 && lnb < nvalid) {
-      lds_line<P, T, 0>(s + lnb * Ly::NP, ta, tb, nb[side]);
-    } else {
-      const uint32_t en = side ? e + estride : e - estride;
-      global_line<P, T, DIR>(g, en * N, ta, tb, nb[side]);
-    }
-  }
-}
-
 // DOT: every block also writes the sum of x_i y_i over its cells (FP64, fixed
 // order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
 template <int P, typename T, bool KAPPA, bool DOT>
@@ -429,7 +327,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
   __shared__ __attribute__((aligned(16))) T sy[EB * Ly::NP];  // x-line results, then += y-line results
 
-  const BlockCoord bc = block_coord(a);
+  const BlockCoord bc = block_coord(a.blocks);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
@@ -653,7 +551,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
   __shared__ T sy[EB * Ly::NP], sd[EB * Ly::NP];  // x-line results, then += y-line results
 
-  const BlockCoord bc = block_coord(a);
+  const BlockCoord bc = block_coord(a.blocks);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
@@ -752,15 +650,6 @@ __device__ __forceinline__ void fdm_backward(const T* __restrict__ V, const T* t
   }
 }
 
-template <int P, typename T, int DIR>
-__device__ __forceinline__ void lds_store_line(T* __restrict__ sc, int ta, int tb, const T* v) {
-  using Ly = Layout<P>;
-  const int off = DIR == 0 ? Ly::S1 * ta + Ly::S2 * tb : (DIR == 1 ? ta + Ly::S2 * tb : ta + Ly::S1 * tb);
-  constexpr int S = DIR == 0 ? 1 : (DIR == 1 ? Ly::S1 : Ly::S2);
-#pragma unroll
-  for (int j = 0; j < P; ++j) sc[off + j * S] = v[j];
-}
-
 // The x-line part of one cell with the tables (V, lam) of its x variant:
 // forward, divide by lam_x + lam_y + lam_z, backward.
 template <int P, typename T>
@@ -788,7 +677,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   __shared__ T sV[3 * L], sL[3 * P];  // x tables: first cell, interior, last cell
   __shared__ double sh[256];
 
-  const BlockCoord bc = block_coord(a);
+  const BlockCoord bc = block_coord(a.blocks);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
   const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
