@@ -70,7 +70,8 @@ enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1, DG_PROBLEM_DIFFREAC_PAPER
 enum { DG_F64 = 0, DG_F32 = 1 };
 enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
 enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
-enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2 };
+enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2, DG_SOLVE_CHEB_F64 = 3,
+       DG_SOLVE_CHEB_F32 = 4 };
 enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1 };
 
 /* Mesh and operator description (all fields are read by dg_mesh_create). */
@@ -115,14 +116,23 @@ typedef struct {
   int32_t max_outer;        /* IR: refinement steps */
   int32_t check_every;      /* read the residual norm to the host every n iterations */
   int32_t precond;          /* DG_PRECOND_*: preconditioner of every CG in the solve (FP64 CG
-                               and the FP32 inner CG alike) */
+                               and the FP32 inner CG alike; CHEB: of the Chebyshev iteration) */
+  int32_t cheb_degree;      /* CHEB: steps s of the inner Chebyshev iteration, 1..64 (0 -> 8) */
+  int32_t cheb_lanczos;     /* CHEB: CG iterations whose Lanczos coefficients estimate the
+                               largest eigenvalue, 2..64 (0 -> 20) */
+  double cheb_ratio;        /* CHEB: b / a of the Chebyshev interval [a, b], > 1 (0 -> max(s^2, 16)) */
+  double cheb_margin;       /* CHEB: b = margin x the largest Ritz value, >= 1 (0 -> 1.1) */
 } dg_solve_params;
 
 typedef struct {
-  int32_t iterations;       /* CG iterations (FP64 CG) or total inner iterations (IR) */
+  int32_t iterations;       /* CG iterations (FP64 CG; CHEB: FP64 CG iterations including the
+                               estimate) or total inner iterations (IR, RU) */
   int32_t outer;            /* refinement steps / residual replacements (0 for FP64 CG) */
   double rel_residual;      /* true ||b - A x||_2 / ||b||_2 in FP64 at exit */
   double seconds;           /* wall time of the solve, host clock */
+  int32_t inner_applies;    /* CHEB: operator applies of the inner Chebyshev iterations */
+  int32_t pad;
+  double lambda_max;        /* CHEB: the largest Ritz value of the estimate (of P A, or of A) */
 } dg_solve_info;
 
 /* Checks a descriptor without touching the GPU (Section 2.1 restrictions:
@@ -178,6 +188,18 @@ dg_status dg_precond_apply(const dg_mesh* mesh, int precision, const void* r, vo
  *    since the last correction (checked every check_every iterations), the FP32
  *    iterate is added to x in FP64, the residual is replaced by the true
  *    FP64 b - A x and the search direction is kept.
+ *  DG_SOLVE_CHEB_F32: FP64 CG preconditioned by a fixed polynomial of the
+ *    FP32 operator: each CG iteration (FP64 apply, FP64 residual, inner
+ *    products and update) solves A z = r approximately by s steps of the
+ *    Chebyshev iteration on the FP32 operator (FP32 vectors, s - 1 FP32
+ *    applies; with the block-Jacobi preconditioner P, the Chebyshev
+ *    iteration of P A). The iteration has no inner products, so FP32
+ *    rounding does not accumulate through a Krylov recursion. Its interval
+ *    [b / cheb_ratio, b] comes from b = cheb_margin x the largest Ritz value
+ *    of the Lanczos coefficients of the first cheb_lanczos FP64 CG
+ *    iterations, which the solve runs first (they advance x as well).
+ *  DG_SOLVE_CHEB_F64: the same with the inner iteration in FP64 (the
+ *    baseline that isolates the gain of the FP32 inner work).
  * b, x: device FP64 vectors; x holds the initial guess on entry. kappa as in
  * dg_apply (FP64 values; the FP32 operator rounds them). Synchronous. */
 dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
@@ -190,9 +212,10 @@ dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, co
  * bitwise), but its vectors, partial sums and CG state live in one fixed
  * 64 MiB device array per GPU, held until the process ends, and the state is
  * read back to ordinary host memory. A solve needs about 24 bytes per DOF
- * (FP64 CG), 32 (FP64 CG with block-Jacobi) or 36-40 (the FP32 refinement
- * modes), so meshes up to about 1.6 million DOFs fit in every mode; a larger
- * one returns DG_ERR_ARG with the bytes it would need. Every call on a GPU
+ * (FP64 CG), 32 (FP64 CG with block-Jacobi), 36-40 (the FP32 refinement
+ * modes) or 40-48 (the Chebyshev modes), so meshes up to about 1.3 million
+ * DOFs fit in every mode; a larger one returns DG_ERR_ARG with the bytes it
+ * would need. Every call on a GPU
  * uses that GPU's one array: calls that overlap in time on the same GPU (from
  * several threads or streams) race and must be serialized by the caller. The
  * array keeps the last call's contents; every piece of it is written before

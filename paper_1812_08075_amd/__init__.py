@@ -27,7 +27,7 @@ DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES, DG_PROBLEM_DIFFREAC_PAPER = 0, 1, 2
 DG_F64, DG_F32 = 0, 1
 DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
 DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
-DG_SOLVE_CG_F64, DG_SOLVE_IR_F32, DG_SOLVE_RU_F32 = 0, 1, 2
+DG_SOLVE_CG_F64, DG_SOLVE_IR_F32, DG_SOLVE_RU_F32, DG_SOLVE_CHEB_F64, DG_SOLVE_CHEB_F32 = 0, 1, 2, 3, 4
 DG_PRECOND_NONE, DG_PRECOND_BLOCK_JACOBI = 0, 1
 
 _DTYPE = {DG_F64: torch.float64, DG_F32: torch.float32}
@@ -56,12 +56,15 @@ class dg_mesh_info_t(ctypes.Structure):
 
 class dg_solve_params(ctypes.Structure):
     _fields_ = [("rtol", ctypes.c_double), ("inner_rtol", ctypes.c_double), ("maxit", ctypes.c_int32),
-                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32)]
+                ("max_outer", ctypes.c_int32), ("check_every", ctypes.c_int32), ("precond", ctypes.c_int32),
+                ("cheb_degree", ctypes.c_int32), ("cheb_lanczos", ctypes.c_int32),
+                ("cheb_ratio", ctypes.c_double), ("cheb_margin", ctypes.c_double)]
 
 
 class dg_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
-                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double)]
+                ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("inner_applies", ctypes.c_int32), ("pad", ctypes.c_int32), ("lambda_max", ctypes.c_double)]
 
 
 # every symbol include/dg.h declares
@@ -251,10 +254,12 @@ def dg_precond_apply(mesh, precision, r, z, stream=None):
 
 
 def dg_solve(mesh, mode, b, x, kappa=None, rtol=1e-10, inner_rtol=1e-5, maxit=100000, max_outer=50,
-             check_every=10, precond=DG_PRECOND_NONE, stream=None, noalloc=False):
+             check_every=10, precond=DG_PRECOND_NONE, stream=None, noalloc=False, cheb_degree=0,
+             cheb_lanczos=0, cheb_ratio=0.0, cheb_margin=0.0):
     """dg_solve, or with noalloc=True dg_solve_noalloc (fixed device workspace)."""
     n, nq = _sizes(mesh)
-    params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every, precond)
+    params = dg_solve_params(rtol, inner_rtol, maxit, max_outer, check_every, precond, cheb_degree, cheb_lanczos,
+                             cheb_ratio, cheb_margin)
     info = dg_solve_info()
     fn = _lib().dg_solve_noalloc if noalloc else _lib().dg_solve
     st = _check(fn(mesh, mode, _vec(b, n, DG_F64, "b"), _vec(x, n, DG_F64, "x"),

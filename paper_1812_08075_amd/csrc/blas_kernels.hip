@@ -36,13 +36,31 @@ __global__ void __launch_bounds__(RT) k_dot(const T* __restrict__ a, const T* __
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// Sums the partials (fixed order) and applies `op` to the CG state.
-__global__ void __launch_bounds__(RT) k_finalize(const double* __restrict__ partial, int nb,
+// Sums the partials (fixed order) and applies `op` to the CG state. FT
+// threads: thread i adds partial[i], partial[i + FT], ... in order, four
+// independent loads at a time, then a tree over the block.
+constexpr int FT = 1024;
+__global__ void __launch_bounds__(FT) k_finalize(const double* __restrict__ partial, int nb,
                                                  CgState* __restrict__ st, int op) {
-  __shared__ double sh[RT];
+  __shared__ double sh[FT];
   double acc = 0.0;
-  for (int i = threadIdx.x; i < nb; i += RT) acc += partial[i];
-  const double s = block_sum(acc, sh);
+  int i = threadIdx.x;
+  for (; i + 3 * FT < nb; i += 4 * FT) {
+    const double a0 = partial[i], a1 = partial[i + FT], a2 = partial[i + 2 * FT], a3 = partial[i + 3 * FT];
+    acc += a0;
+    acc += a1;
+    acc += a2;
+    acc += a3;
+  }
+  for (; i < nb; i += FT) acc += partial[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int s = FT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+    __syncthreads();
+  }
+  const double s = sh[0];
   if (threadIdx.x != 0) return;
   switch (op) {
     case OP_SET_RR:
@@ -126,6 +144,72 @@ __global__ void __launch_bounds__(RT) k_xp_update(T* __restrict__ x, T* __restri
   }
 }
 
+// r -= alpha q (FP64) with partial sums of r.r, and r32 = r rounded to FP32
+// (the right-hand side of the FP32 Chebyshev inner solve)
+__global__ void __launch_bounds__(RT) k_r_update_round(double* __restrict__ r, const double* __restrict__ q,
+                                                       float* __restrict__ r32, const CgState* __restrict__ st,
+                                                       int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[RT];
+  const double a = st->alpha;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    const double ri = fma(-a, q[i], r[i]);
+    r[i] = ri;
+    r32[i] = (float)ri;
+    acc = fma(ri, ri, acc);
+  }
+  const double s = block_sum(acc, sh);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// x += alpha p; p = z + beta p with the preconditioned residual z in FP32
+__global__ void __launch_bounds__(RT) k_xp_update_mixed(double* __restrict__ x, double* __restrict__ p,
+                                                        const float* __restrict__ z,
+                                                        const CgState* __restrict__ st, int64_t n) {
+  const double a = st->alpha, b = st->beta;
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    const double pi = p[i];
+    x[i] = fma(a, pi, x[i]);
+    p[i] = fma(b, pi, (double)z[i]);
+  }
+}
+
+// One step of the Chebyshev iteration for A z = r without a preconditioner:
+// w = r - t (t = A z; absent on the first step, where z = 0), d = c1 d + c2 w
+// (d absent on the first step), z += d. The right-hand side is read from rd
+// (FP64, rounded to T) when given, else from r; with rd the last step also
+// writes the partial sums of rd.z (FP64) and skips the store of d.
+template <typename T>
+__global__ void __launch_bounds__(RT) k_cheb_plain(const T* __restrict__ r, const double* __restrict__ rd,
+                                                   const T* __restrict__ t, T* __restrict__ d,
+                                                   T* __restrict__ z, T c1, T c2, int first, int last,
+                                                   int64_t n, double* __restrict__ partial) {
+  __shared__ double sh[RT];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    const T ri = rd ? (T)rd[i] : r[i];
+    const T wi = first ? ri : ri - t[i];
+    const T di = first ? c2 * wi : fma(c1, d[i], c2 * wi);
+    const T zi = first ? di : z[i] + di;
+    if (!last) d[i] = di;
+    z[i] = zi;
+    if (last && rd) acc = fma(rd[i], (double)zi, acc);
+  }
+  if (last && rd) {
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  }
+}
+
+// Records the step length and direction update of the CG iteration just done
+// (the Lanczos coefficients of the spectral estimate).
+__global__ void k_record(const CgState* __restrict__ st, double* __restrict__ hist, int j) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    hist[2 * j] = st->alpha;
+    hist[2 * j + 1] = st->beta;
+  }
+}
+
 // r = b - Ax (FP64); partial sums of r.r
 __global__ void __launch_bounds__(RT) k_residual(const double* __restrict__ b, const double* __restrict__ Ax,
                                                  double* __restrict__ r, int64_t n, double* __restrict__ partial) {
@@ -179,6 +263,10 @@ __global__ void __launch_bounds__(RT) k_copy(const T* __restrict__ a, T* __restr
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) b[i] = a[i];
 }
 
+__global__ void __launch_bounds__(RT) k_widen(const float* __restrict__ a, double* __restrict__ b, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) b[i] = (double)a[i];
+}
+
 __global__ void __launch_bounds__(RT) k_round_f32(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) b[i] = (float)a[i];
 }
@@ -217,13 +305,13 @@ hipError_t blas_dot(const void* a, const void* b, int prec, int64_t n, double* p
     hipLaunchKernelGGL(k_dot<double>, dim3(g), dim3(RT), 0, s, (const double*)a, (const double*)b, n, partial);
   else
     hipLaunchKernelGGL(k_dot<float>, dim3(g), dim3(RT), 0, s, (const float*)a, (const float*)b, n, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, op);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FT), 0, s, partial, (int)g, st, op);
   return hipGetLastError();
 }
 
 hipError_t blas_finalize(const double* partial, int64_t nb, CgState* st, int op, hipStream_t s) {
   if (nb < 1 || nb > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)nb, st, op);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FT), 0, s, partial, (int)nb, st, op);
   return hipGetLastError();
 }
 
@@ -234,7 +322,7 @@ hipError_t blas_r_update(void* r, const void* q, int prec, int64_t n, double* pa
     hipLaunchKernelGGL(k_r_update<double>, dim3(g), dim3(RT), 0, s, (double*)r, (const double*)q, st, n, partial);
   else
     hipLaunchKernelGGL(k_r_update<float>, dim3(g), dim3(RT), 0, s, (float*)r, (const float*)q, st, n, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, op);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FT), 0, s, partial, (int)g, st, op);
   return hipGetLastError();
 }
 
@@ -248,11 +336,43 @@ hipError_t blas_xp_update(void* x, void* p, const void* z, int prec, int64_t n, 
   return hipGetLastError();
 }
 
+hipError_t blas_r_update_round(double* r, const double* q, float* r32, int64_t n, double* partial, CgState* st,
+                               int op, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  hipLaunchKernelGGL(k_r_update_round, dim3(g), dim3(RT), 0, s, r, q, r32, st, n, partial);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FT), 0, s, partial, (int)g, st, op);
+  return hipGetLastError();
+}
+
+hipError_t blas_xp_update_mixed(double* x, double* p, const float* z, int64_t n, CgState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_xp_update_mixed, dim3(grid_for(n)), dim3(RT), 0, s, x, p, z, st, n);
+  return hipGetLastError();
+}
+
+int64_t blas_cheb_blocks(int64_t n) { return grid_for(n); }
+
+hipError_t blas_cheb_step(int prec, const void* r, const double* rd, const void* t, void* d, void* z, double c1,
+                          double c2, bool first, bool last, int64_t n, double* partial, hipStream_t s) {
+  const unsigned g = grid_for(n);
+  if (prec == DG_F64)
+    hipLaunchKernelGGL(k_cheb_plain<double>, dim3(g), dim3(RT), 0, s, (const double*)r, rd, (const double*)t,
+                       (double*)d, (double*)z, c1, c2, (int)first, (int)last, n, partial);
+  else
+    hipLaunchKernelGGL(k_cheb_plain<float>, dim3(g), dim3(RT), 0, s, (const float*)r, rd, (const float*)t,
+                       (float*)d, (float*)z, (float)c1, (float)c2, (int)first, (int)last, n, partial);
+  return hipGetLastError();
+}
+
+hipError_t blas_record(const CgState* st, double* hist, int j, hipStream_t s) {
+  hipLaunchKernelGGL(k_record, dim3(1), dim3(1), 0, s, st, hist, j);
+  return hipGetLastError();
+}
+
 hipError_t blas_residual(const double* b, const double* Ax, double* r, int64_t n, double* partial, CgState* st,
                          hipStream_t s) {
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_residual, dim3(g), dim3(RT), 0, s, b, Ax, r, n, partial);
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(RT), 0, s, partial, (int)g, st, (int)OP_NORM);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(FT), 0, s, partial, (int)g, st, (int)OP_NORM);
   return hipGetLastError();
 }
 
@@ -290,6 +410,11 @@ hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s)
 
 hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_round_f32, dim3(grid_for(n)), dim3(RT), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_widen(const float* a, double* b, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_widen, dim3(grid_for(n)), dim3(RT), 0, s, a, b, n);
   return hipGetLastError();
 }
 

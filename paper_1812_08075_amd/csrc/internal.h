@@ -216,6 +216,13 @@ hipError_t block_jacobi(const dg_mesh& M, int prec, const void* r, void* z, doub
 hipError_t block_jacobi_update(const dg_mesh& M, int prec, void* r, const void* q, const double* alpha, void* z,
                                double* partial_rz, double* partial_rr, hipStream_t s);
 int64_t block_jacobi_blocks(const dg_mesh& M);
+// One step of the Chebyshev iteration preconditioned by the block-Jacobi
+// inverse P (k_cheb_block_jacobi): z += d, d = c1 d + c2 P (rhs - t); the first
+// step has t = d = z = 0; the rhs is rd (FP64, rounded) when given, else r;
+// with rd the last step writes the partial sums of rd.z
+// (block_jacobi_blocks(M) entries) and does not store d.
+hipError_t cheb_block_jacobi(const dg_mesh& M, int prec, const void* r, const double* rd, const void* t, void* d,
+                             void* z, double c1, double c2, bool first, bool last, double* partial, hipStream_t s);
 inline bool block_jacobi_supported(const dg_mesh& M) { return M.pd[SP_APPLY].fdm_ok != 0; }
 // Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,
 // line weights) and uploads them to M.d_pd / M.d_pf (allocated by the caller).

@@ -661,6 +661,91 @@ __device__ __forceinline__ void fdm_x(const T* V, const T* lam, T lyz, T* v) {
   fdm_backward<P, T>(V, o, v);
 }
 
+// Side-type variants of a block's cells for the preconditioner tables: y and
+// z are block-uniform, x differs for the first and last cells of a row; the
+// block's three possible x tables (its first cell's, the interior one, its
+// last cell's) are staged in LDS.
+struct FdmVariants {
+  int vx, vy, vz, vfirst, vlast;
+};
+
+template <int P, typename T>
+__device__ __forceinline__ FdmVariants fdm_setup(const ScalarArgs<T>& a, const BlockCoord& bc, int nvalid, int le,
+                                                 T* sV, T* sL) {
+  constexpr int L = P * P;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const uint32_t mask = a.mask;
+  FdmVariants v;
+  v.vx = fdm_variant(bc.ex0 + le, nx, mask, 0);
+  // block-uniform (made explicit so that the tables are read with scalar loads)
+  v.vy = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ey, ny, mask, 1));
+  v.vz = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ez, nz, mask, 2));
+  v.vfirst = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0, nx, mask, 0));
+  v.vlast = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0 + nvalid - 1, nx, mask, 0));
+  for (int i = threadIdx.x; i < 3 * (L + P); i += blockDim.x) {
+    const int k = i / (L + P), e = i - k * (L + P);
+    const int u = k == 0 ? v.vfirst : (k == 1 ? 0 : v.vlast);
+    if (e < L) sV[k * L + e] = a.fdmV[0][u][e];
+    else sL[k * P + e - L] = a.fdmL[0][u][e - L];
+  }
+  return v;
+}
+
+// o = B_T^-1 rv for the thread's column (ta, tb, 0..P-1) of its cell, by the
+// five phases of fast diagonalization through the cell's LDS block sc. Every
+// thread of the block calls it (it synchronizes); inactive threads pass
+// active = false.
+template <int P, typename T>
+__device__ __forceinline__ void fdm_solve(const ScalarArgs<T>& a, T* sc, const T* sV, const T* sL,
+                                          const FdmVariants& fv, bool active, int ta, int tb, const T* rv, T* o) {
+  constexpr int L = P * P;
+  T v[P], w[P];
+  if (active) {  // z-lines: the thread's own column
+    fdm_forward<P, T>(a.fdmV[2][fv.vz], rv, w);
+    lds_store_line<P, T, 2>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {  // y-lines (i0, i2) = (ta, tb)
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_forward<P, T>(a.fdmV[1][fv.vy], v, w);
+    lds_store_line<P, T, 1>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {  // x-lines (i1, i2) = (ta, tb), the cell's x tables from LDS
+    lds_line<P, T, 0>(sc, ta, tb, v);
+    const int slot = fv.vx == fv.vfirst ? 0 : (fv.vx == fv.vlast ? 2 : 1);
+    fdm_x<P, T>(sV + slot * L, sL + slot * P, a.fdmL[1][fv.vy][ta] + a.fdmL[2][fv.vz][tb], v);
+    lds_store_line<P, T, 0>(sc, ta, tb, v);
+  }
+  __syncthreads();
+  if (active) {
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[1][fv.vy], v, w);
+    lds_store_line<P, T, 1>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {
+    lds_line<P, T, 2>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[2][fv.vz], v, o);
+  }
+}
+
+// Fixed-order tree sum of one value per thread over the block (NT threads,
+// NT in [128, 256]) into out[blockIdx.x]; sh: 256 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void block_sum_to(double val, double* sh, double* out) {
+  if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
+  sh[threadIdx.x] = val;
+  __syncthreads();
+#pragma unroll
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+  __syncthreads();
+}
+
 // With q != NULL the residual is first updated in place, r -= alpha q (alpha
 // read from device memory), and partial sums of r.r go to partial_rr: one
 // pass over r, q and z per conjugate-gradient iteration.
@@ -678,7 +763,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   __shared__ double sh[256];
 
   const BlockCoord bc = block_coord(a.blocks);
-  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const int nx = a.n[0], ny = a.n[1];
   const int ex0 = bc.ex0;
   const int nvalid = min(EB, nx - ex0);
   const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
@@ -686,24 +771,10 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const int li = threadIdx.x - le * L;
   const bool active = le < nvalid;
   const int ta = li % P, tb = li / P;
-  const uint32_t mask = a.mask;
-  const int vx = fdm_variant(ex0 + le, nx, mask, 0);
-  // x variants in the block: its first cell's, the interior one, its last cell's
-  // block-uniform (made explicit so that the tables are read with scalar loads)
-  const int vy = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ey, ny, mask, 1));
-  const int vz = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ez, nz, mask, 2));
-  const int vfirst = __builtin_amdgcn_readfirstlane(fdm_variant(ex0, nx, mask, 0));
-  const int vlast = __builtin_amdgcn_readfirstlane(fdm_variant(ex0 + nvalid - 1, nx, mask, 0));
-  T* sc = s + le * Ly::NP;
-  for (int i = threadIdx.x; i < 3 * (L + P); i += NT) {
-    const int k = i / (L + P), e = i - k * (L + P);
-    const int u = k == 0 ? vfirst : (k == 1 ? 0 : vlast);
-    if (e < L) sV[k * L + e] = a.fdmV[0][u][e];
-    else sL[k * P + e - L] = a.fdmL[0][u][e - L];
-  }
+  const FdmVariants fv = fdm_setup<P, T>(a, bc, nvalid, le, sV, sL);
   // the thread's column (ta, tb, 0..P-1) is the z-line it owns first
   const size_t col = (size_t)(row + ex0 + le) * N + ta + P * tb;
-  T rv[P], v[P], o[P];
+  T rv[P], o[P];
   double rr = 0.0;
   if (active) {
     if (q) {
@@ -718,54 +789,74 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
 #pragma unroll
       for (int j = 0; j < P; ++j) rv[j] = r[col + (size_t)j * L];
     }
-    fdm_forward<P, T>(a.fdmV[2][vz], rv, o);
-    lds_store_line<P, T, 2>(sc, ta, tb, o);
   }
-  __syncthreads();
-  if (active) {  // y-lines (i0, i2) = (ta, tb)
-    lds_line<P, T, 1>(sc, ta, tb, v);
-    fdm_forward<P, T>(a.fdmV[1][vy], v, o);
-    lds_store_line<P, T, 1>(sc, ta, tb, o);
-  }
-  __syncthreads();
-  if (active) {  // x-lines (i1, i2) = (ta, tb), the cell's x tables from LDS
-    lds_line<P, T, 0>(sc, ta, tb, v);
-    const int slot = vx == vfirst ? 0 : (vx == vlast ? 2 : 1);
-    fdm_x<P, T>(sV + slot * L, sL + slot * P, a.fdmL[1][vy][ta] + a.fdmL[2][vz][tb], v);
-    lds_store_line<P, T, 0>(sc, ta, tb, v);
-  }
-  __syncthreads();
-  if (active) {
-    lds_line<P, T, 1>(sc, ta, tb, v);
-    fdm_backward<P, T>(a.fdmV[1][vy], v, o);
-    lds_store_line<P, T, 1>(sc, ta, tb, o);
-  }
-  __syncthreads();
+  fdm_solve<P, T>(a, s + le * Ly::NP, sV, sL, fv, active, ta, tb, rv, o);
   double rz = 0.0;
   if (active) {
-    lds_line<P, T, 2>(sc, ta, tb, v);
-    fdm_backward<P, T>(a.fdmV[2][vz], v, o);
 #pragma unroll
     for (int j = 0; j < P; ++j) {
       z[col + (size_t)j * L] = o[j];
       rz = fma((double)rv[j], (double)o[j], rz);
     }
   }
-  // block sums in a fixed-order tree (NT >= 128): r.z, then r.r
-  auto block_sum_to = [&](double val, double* out) {
-    if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
-    sh[threadIdx.x] = val;
-    __syncthreads();
+  // block sums: r.z, then r.r
+  if (partial) block_sum_to<NT>(rz, sh, partial);
+  if (q) block_sum_to<NT>(rr, sh, partial_rr);
+}
+
+// One step of the Chebyshev iteration for B z = rhs preconditioned by the
+// block-Jacobi inverse P: w = P (rhs - t) (t = A z; absent on the first
+// step, where z = 0), d = c1 d + c2 w (d absent on the first step), z += d.
+// The right-hand side is read from rd (FP64, rounded to T) when given, else
+// from r; with rd the last step also writes the partial sums of rd.z (FP64,
+// fixed order) and does not store d.
+template <int P, typename T>
+__global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
+    k_cheb_block_jacobi(const T* __restrict__ r, const double* __restrict__ rd, const T* __restrict__ t,
+                        T* __restrict__ d, T* __restrict__ z, T c1, T c2, int first, int last,
+                        const ScalarArgs<T>* __restrict__ ap, double* __restrict__ partial) {
+  const ScalarArgs<T>& a = *ap;
+  constexpr int EB = CellsPerBlock<P>::value;
+  constexpr int L = P * P, N = P * P * P, NT = EB * L;
+  using Ly = Layout<P>;
+  __shared__ T s[EB * Ly::NP];
+  __shared__ T sV[3 * L], sL[3 * P];
+  __shared__ double sh[256];
+
+  const BlockCoord bc = block_coord(a.blocks);
+  const int nx = a.n[0], ny = a.n[1];
+  const int ex0 = bc.ex0;
+  const int nvalid = min(EB, nx - ex0);
+  const uint32_t row = (uint32_t)nx * ((uint32_t)bc.ey + (uint32_t)ny * bc.ez);
+  const int le = threadIdx.x / L;
+  const int li = threadIdx.x - le * L;
+  const bool active = le < nvalid;
+  const int ta = li % P, tb = li / P;
+  const FdmVariants fv = fdm_setup<P, T>(a, bc, nvalid, le, sV, sL);
+  const size_t col = (size_t)(row + ex0 + le) * N + ta + P * tb;
+  T wv[P], o[P];
+  if (active) {
 #pragma unroll
-    for (int st = 128; st > 0; st >>= 1) {
-      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-      __syncthreads();
+    for (int j = 0; j < P; ++j) {
+      const size_t i = col + (size_t)j * L;
+      const T ri = rd ? (T)rd[i] : r[i];
+      wv[j] = first ? ri : ri - t[i];
     }
-    if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
-    __syncthreads();
-  };
-  if (partial) block_sum_to(rz, partial);
-  if (q) block_sum_to(rr, partial_rr);
+  }
+  fdm_solve<P, T>(a, s + le * Ly::NP, sV, sL, fv, active, ta, tb, wv, o);
+  double rz = 0.0;
+  if (active) {
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const size_t i = col + (size_t)j * L;
+      const T di = first ? c2 * o[j] : fma(c1, d[i], c2 * o[j]);
+      const T zi = first ? di : z[i] + di;
+      if (!last) d[i] = di;
+      z[i] = zi;
+      if (last && rd) rz = fma(rd[i], (double)zi, rz);
+    }
+  }
+  if (last && rd) block_sum_to<NT>(rz, sh, partial);
 }
 
 // b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
@@ -855,6 +946,19 @@ hipError_t launch_block_jacobi(const dg_mesh& M, T* r, T* z, double* partial, co
   return hipGetLastError();
 }
 
+template <int P, typename T>
+hipError_t launch_cheb_block_jacobi(const dg_mesh& M, const T* r, const double* rd, const T* t, T* d, T* z, T c1,
+                                    T c2, bool first, bool last, double* partial, hipStream_t s) {
+  constexpr int EB = CellsPerBlock<P>::value;
+  static_assert(EB * P * P >= 128 && EB * P * P <= 256, "block reduction assumes 128..256 threads");
+  const int64_t G = grid_of(host_params<T>(M)[SP_APPLY]);
+  if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const ScalarArgs<T>* ap = device_params<T>(M) + SP_APPLY;
+  hipLaunchKernelGGL((k_cheb_block_jacobi<P, T>), dim3((unsigned)G), dim3(EB * P * P), 0, s, r, rd, t, d, z, c1, c2,
+                     (int)first, (int)last, ap, partial);
+  return hipGetLastError();
+}
+
 // Cells per block of the apply and adjoint kernels for p nodes per direction.
 int apply_cells_per_block(int p) { return 256 / (p * p) > 0 ? 256 / (p * p) : 1; }
 int adjoint_cells_per_block(int p) { return 128 / (p * p) > 0 ? 128 / (p * p) : 1; }
@@ -891,6 +995,14 @@ template <typename T>
 hipError_t dispatch_block_jacobi(const dg_mesh& M, T* r, T* z, double* partial, const T* q, const double* alpha,
                                  double* partial_rr, hipStream_t s) {
 #define DG_CALL(PP) launch_block_jacobi<PP, T>(M, r, z, partial, q, alpha, partial_rr, s)
+  DG_DISPATCH_P(M.p, DG_CALL)
+#undef DG_CALL
+}
+
+template <typename T>
+hipError_t dispatch_cheb_block_jacobi(const dg_mesh& M, const T* r, const double* rd, const T* t, T* d, T* z, T c1,
+                                      T c2, bool first, bool last, double* partial, hipStream_t s) {
+#define DG_CALL(PP) launch_cheb_block_jacobi<PP, T>(M, r, rd, t, d, z, c1, c2, first, last, partial, s)
   DG_DISPATCH_P(M.p, DG_CALL)
 #undef DG_CALL
 }
@@ -1027,6 +1139,16 @@ hipError_t block_jacobi_update(const dg_mesh& M, int prec, void* r, const void* 
 }
 
 int64_t block_jacobi_blocks(const dg_mesh& M) { return grid_of(M.pd[SP_APPLY]); }
+
+hipError_t cheb_block_jacobi(const dg_mesh& M, int prec, const void* r, const double* rd, const void* t, void* d,
+                             void* z, double c1, double c2, bool first, bool last, double* partial, hipStream_t s) {
+  if (last && rd && !partial) return hipErrorInvalidValue;
+  if (prec == DG_F64)
+    return dispatch_cheb_block_jacobi<double>(M, (const double*)r, rd, (const double*)t, (double*)d, (double*)z, c1,
+                                              c2, first, last, partial, s);
+  return dispatch_cheb_block_jacobi<float>(M, (const float*)r, rd, (const float*)t, (float*)d, (float*)z, (float)c1,
+                                           (float)c2, first, last, partial, s);
+}
 
 hipError_t scalar_load(const dg_mesh& M, int prec, const void* fq, void* b, hipStream_t s) {
   if (prec == DG_F64) return dispatch_load<double>(M, (const double*)fq, (double*)b, s);

@@ -18,6 +18,17 @@
 // search direction is kept, so the convergence of the Krylov space is not
 // restarted.
 //
+// Chebyshev-preconditioned CG (DG_SOLVE_CHEB_F32 / _F64): FP64 CG whose
+// preconditioner is s steps of the Chebyshev iteration for A z = r (with the
+// block-Jacobi inverse P: for P A z = P r) on the interval [b / ratio, b], run
+// on the FP32 (or FP64) operator from z = 0. The map r -> z is a fixed
+// polynomial in P A times P, symmetric and positive definite when the
+// spectrum of P A lies in (0, b], so the outer iteration is ordinary PCG;
+// the inner iteration takes no inner products, and FP32 rounding in it only
+// perturbs the preconditioner. b is cheb_margin times the largest eigenvalue
+// of the Lanczos matrix built from the step lengths and direction updates of
+// the first FP64 CG iterations, which the solve runs first.
+//
 // Convergence is declared on the true FP64 residual |b - A x| <= rtol |b| in
 // every mode.
 //
@@ -74,9 +85,62 @@ struct Work {
   double* q = nullptr;         // FP64 scratch (A x, A p)
   double* p = nullptr;         // FP64 CG: search direction
   double* z = nullptr;         // FP64 PCG: preconditioned residual
-  float* f[5] = {};            // FP32 CG: residual, direction, A p, iterate, preconditioned residual
+  float* f[5] = {};            // FP32 CG: residual, direction, A p, iterate, preconditioned residual;
+                               // FP32 Chebyshev: right-hand side, iterate, step, A z
+  double* d = nullptr;         // FP64 Chebyshev: step
+  double* t = nullptr;         // FP64 Chebyshev: A z
+  double* hist = nullptr;      // Lanczos coefficients (alpha, beta) of the first CG iterations
   float* k32 = nullptr;        // kappa rounded to FP32
 };
+
+constexpr int kMaxLanczos = 64;
+constexpr int kMaxChebDegree = 64;
+
+bool cheb_mode(int mode) { return mode == DG_SOLVE_CHEB_F32 || mode == DG_SOLVE_CHEB_F64; }
+
+// Largest eigenvalue of the Lanczos matrix of k CG iterations with step
+// lengths alpha_j and direction updates beta_j (hist[2j], hist[2j+1]): the
+// symmetric tridiagonal T with T_jj = 1/alpha_j + beta_{j-1}/alpha_{j-1} and
+// T_{j,j+1} = sqrt(beta_j)/alpha_j, whose eigenvalues are the Ritz values of
+// the (preconditioned) operator on the Krylov space. Bisection on the Sturm
+// count inside the Gershgorin interval. Returns 0 if a coefficient is not a
+// positive finite number.
+double lanczos_max(const double* hist, int k) {
+  double dg[kMaxLanczos], off[kMaxLanczos];
+  for (int j = 0; j < k; ++j) {
+    const double al = hist[2 * j];
+    if (!(al > 0.0) || !std::isfinite(al)) return 0.0;
+    dg[j] = 1.0 / al;
+    if (j > 0) dg[j] += hist[2 * j - 1] / hist[2 * j - 2];
+    if (j + 1 < k) {
+      const double be = hist[2 * j + 1];
+      if (!(be >= 0.0) || !std::isfinite(be)) return 0.0;
+      off[j] = std::sqrt(be) / al;
+    }
+  }
+  double lo = 0.0, hi = 0.0;
+  for (int j = 0; j < k; ++j) {
+    const double r = (j > 0 ? off[j - 1] : 0.0) + (j + 1 < k ? off[j] : 0.0);
+    hi = std::max(hi, dg[j] + r);
+  }
+  // number of eigenvalues of T smaller than x
+  auto count_below = [&](double x) {
+    int c = 0;
+    double q = dg[0] - x;
+    if (q < 0) ++c;
+    for (int j = 1; j < k; ++j) {
+      const double den = q != 0.0 ? q : 1e-300;
+      q = dg[j] - x - off[j - 1] * off[j - 1] / den;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200 && hi - lo > 1e-14 * hi; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= k) hi = mid; else lo = mid;
+  }
+  return hi;
+}
 
 // Lays out the memory of a solve from `base` (nullptr: only counts) and
 // returns its size in bytes. Every piece starts on a 256-byte boundary.
@@ -91,6 +155,7 @@ size_t layout(const dg_mesh& M, int mode, bool pc, bool kap, char* base, Work* w
   const size_t n = (size_t)M.ndofs;
   int64_t np = std::max(dgi::scalar_apply_blocks(M, DG_F64, kap), dgi::scalar_apply_blocks(M, DG_F32, kap));
   np = std::max<int64_t>(np, dgi::RED_BLOCKS);
+  np = std::max<int64_t>(np, dgi::blas_cheb_blocks((int64_t)n));
   if (pc) np = std::max(np, dgi::block_jacobi_blocks(M));
   w->partial = (double*)take(sizeof(double) * np);
   if (pc) w->partial2 = (double*)take(sizeof(double) * np);
@@ -100,6 +165,17 @@ size_t layout(const dg_mesh& M, int mode, bool pc, bool kap, char* base, Work* w
   if (mode == DG_SOLVE_CG_F64) {
     w->p = (double*)take(sizeof(double) * n);
     if (pc) w->z = (double*)take(sizeof(double) * n);
+  } else if (cheb_mode(mode)) {
+    w->hist = (double*)take(sizeof(double) * 2 * kMaxLanczos);
+    w->p = (double*)take(sizeof(double) * n);
+    if (pc || mode == DG_SOLVE_CHEB_F64) w->z = (double*)take(sizeof(double) * n);
+    if (mode == DG_SOLVE_CHEB_F64) {
+      w->d = (double*)take(sizeof(double) * n);
+      w->t = (double*)take(sizeof(double) * n);
+    } else {
+      for (int i = 0; i < 4; ++i) w->f[i] = (float*)take(sizeof(float) * n);
+      if (kap) w->k32 = (float*)take(sizeof(float) * (size_t)M.nqp);
+    }
   } else {
     for (int i = 0; i < 4; ++i) w->f[i] = (float*)take(sizeof(float) * n);
     if (pc) w->f[4] = (float*)take(sizeof(float) * n);
@@ -169,6 +245,36 @@ class Solver {
     }
   }
 
+  // z = C r: s steps of the Chebyshev iteration for (P) A z = (P) r from z = 0
+  // on [lo, hi], in precision `prec` (rin: the right-hand side in that
+  // precision; rd: the same in FP64, from which the last step reads it and
+  // forms r.z), then r.z reduced into the state with `op`.
+  void cheb_precond(int prec, const void* rin, const double* rd, void* z, void* d, void* t, const void* kappa,
+                    int s, double lo, double hi, int op, int* applies) {
+    const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < s; ++k) {
+      const bool first = k == 0, last = k == s - 1;
+      double c1 = 0.0, c2 = 1.0 / theta;
+      if (!first) {
+        apply(prec, z, t, kappa);
+        ++*applies;
+        const double rho_new = 1.0 / (2.0 * sigma - rho);
+        c1 = rho_new * rho;
+        c2 = 2.0 * rho_new / delta;
+        rho = rho_new;
+      }
+      if (pc_)
+        ck(dgi::cheb_block_jacobi(M_, prec, rin, last ? rd : nullptr, t, d, z, c1, c2, first, last, partial(), s_),
+           "Chebyshev step");
+      else
+        ck(dgi::blas_cheb_step(prec, rin, last ? rd : nullptr, t, d, z, c1, c2, first, last, n_, partial(), s_),
+           "Chebyshev step");
+    }
+    const int64_t nb = pc_ ? dgi::block_jacobi_blocks(M_) : dgi::blas_cheb_blocks(n_);
+    ck(dgi::blas_finalize(partial(), nb, st(), op, s_), "r.z");
+  }
+
   // nrm2 = |b - A x|^2 with r = b - A x (q is scratch)
   double true_residual(const double* b, const double* x, double* r, double* q) {
     apply(DG_F64, x, q, kappa_);
@@ -228,6 +334,9 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
   info->outer = 0;
   info->rel_residual = 0.0;
   info->seconds = 0.0;
+  info->inner_applies = 0;
+  info->pad = 0;
+  info->lambda_max = 0.0;
   dg_status status = DG_OK;
   if (bnorm == 0.0) {
     ck(dgi::blas_zero(x, DG_F64, n, s), "zero x");
@@ -251,6 +360,96 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       res = std::sqrt(S.true_residual(b, x, r, q));
     }
     info->iterations = total;
+  } else if (cheb_mode(mode)) {
+    const bool f32 = mode == DG_SOLVE_CHEB_F32;
+    const int ip = f32 ? DG_F32 : DG_F64;
+    const int deg = prm->cheb_degree > 0 ? prm->cheb_degree : 8;
+    const int nlz = prm->cheb_lanczos > 0 ? prm->cheb_lanczos : 20;
+    const double ratio = prm->cheb_ratio > 0.0 ? prm->cheb_ratio : std::max(16.0, (double)deg * deg);
+    double margin = prm->cheb_margin > 0.0 ? prm->cheb_margin : 1.1;
+    double* p = w.p;
+    double* zv = w.z;
+    void* zc = f32 ? (void*)w.f[1] : (void*)w.z;  // the Chebyshev iterate
+    void* dc = f32 ? (void*)w.f[2] : (void*)w.d;
+    void* tc = f32 ? (void*)w.f[3] : (void*)w.t;
+    float* r32 = w.f[0];
+    const void* kapc = kappa;
+    if (kappa && f32) {
+      ck(dgi::blas_round_f32((const double*)kappa, w.k32, M->nqp, s), "kappa to FP32");
+      kapc = w.k32;
+    }
+    int total = 0, applies = 0, outer = 0;
+    // 1. the first FP64 (P)CG iterations, recording their Lanczos coefficients
+    ck(dgi::blas_state_from_norm(S.st(), s), "state");
+    S.start_direction(DG_F64, r, p, zv);
+    int nrec = 0;
+    for (; nrec < nlz && total < prm->maxit; ++nrec, ++total) {
+      S.iterate(DG_F64, x, r, p, q, zv, kappa);
+      ck(dgi::blas_record(S.st(), w.hist, nrec, s), "record");
+    }
+    double hist[2 * kMaxLanczos];
+    ck(hipMemcpyAsync(hist, w.hist, sizeof(double) * 2 * nrec, hipMemcpyDeviceToHost, s), "Lanczos readback");
+    (void)S.read();  // also waits for the coefficients
+    // a CG that converged (or broke down) within these iterations leaves a
+    // zero step length behind: the estimate uses the iterations before it
+    int nval = 0;
+    while (nval < nrec && hist[2 * nval] > 0.0 && std::isfinite(hist[2 * nval])) ++nval;
+    const double lmax = nval >= 1 ? lanczos_max(hist, nval) : 0.0;
+    info->lambda_max = lmax;
+    res = std::sqrt(S.true_residual(b, x, r, q));
+    if (res > target && !(lmax > 0.0)) breakdown = 1;
+    // 2. CG preconditioned by the Chebyshev polynomial; restarted from the
+    // true residual when the recursive one has converged but the true one
+    // has not, and with a wider interval if the polynomial lost definiteness
+    int widen = 0;
+    while (res > target && total < prm->maxit && !breakdown) {
+      const double hi = margin * lmax, lo = hi / ratio;
+      ck(dgi::blas_state_from_norm(S.st(), s), "state");
+      if (f32) ck(dgi::blas_round_f32(r, r32, n, s), "r to FP32");
+      S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi, dgi::OP_SET_RZ,
+                     &applies);
+      if (f32) ck(dgi::blas_widen(w.f[1], p, n, s), "p = z");
+      else ck(dgi::blas_copy(zv, p, DG_F64, n, s), "p = z");
+      const int cstep = std::max(1, check / deg);
+      int it = 0, lost = 0;
+      while (total < prm->maxit) {
+        if (it % cstep == 0) {
+          const dgi::CgState h = S.read();
+          if (h.breakdown) {
+            lost = 1;
+            break;
+          }
+          if (std::sqrt(h.rr) <= target) break;
+        }
+        // q = A p and p.Ap; alpha = r.z / p.Ap
+        ck(dgi::scalar_apply(*M, DG_F64, p, q, kappa, false, s, S.partial()), "apply");
+        ck(dgi::blas_finalize(S.partial(), dgi::scalar_apply_blocks(*M, DG_F64, kappa != nullptr), S.st(),
+                              dgi::OP_ALPHA_PC, s),
+           "p.Ap");
+        // r -= alpha q with r.r (and its FP32 copy)
+        if (f32) ck(dgi::blas_r_update_round(r, q, r32, n, S.partial(), S.st(), dgi::OP_RR, s), "residual update");
+        else ck(dgi::blas_r_update(r, q, DG_F64, n, S.partial(), S.st(), dgi::OP_RR, s), "residual update");
+        // z = C r with r.z; beta = r.z / previous r.z
+        S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi,
+                       dgi::OP_BETA_PC, &applies);
+        // x += alpha p; p = z + beta p
+        if (f32) ck(dgi::blas_xp_update_mixed(x, p, w.f[1], n, S.st(), s), "x and p update");
+        else ck(dgi::blas_xp_update(x, p, zv, DG_F64, n, S.st(), s), "x and p update");
+        ++it;
+        ++total;
+      }
+      ++outer;
+      res = std::sqrt(S.true_residual(b, x, r, q));
+      if (lost && res > target) {
+        // a polynomial that is not positive on the spectrum shows as
+        // p.Ap <= 0 or r.z < 0: widen the interval and start again from x
+        if (++widen > 3) breakdown = 1;
+        margin *= 1.5;
+      }
+    }
+    info->iterations = total;
+    info->outer = outer;
+    info->inner_applies = applies;
   } else if (mode == DG_SOLVE_RU_F32) {
     // one FP32 CG whose residual is replaced by the true FP64 residual (and its
     // iterate moved into x) each time it has dropped by RU_DROP since the last
@@ -376,8 +575,15 @@ dg_status check_args(const dg_mesh* M, int mode, const double* b, double* x, con
     dg_set_error("dg_solve is built for the diffusion-reaction operator");
     return DG_ERR_UNSUPPORTED;
   }
-  if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32 && mode != DG_SOLVE_RU_F32) {
+  if (mode != DG_SOLVE_CG_F64 && mode != DG_SOLVE_IR_F32 && mode != DG_SOLVE_RU_F32 && !cheb_mode(mode)) {
     dg_set_error("unknown solve mode");
+    return DG_ERR_ARG;
+  }
+  if (cheb_mode(mode) &&
+      (prm->cheb_degree < 0 || prm->cheb_degree > kMaxChebDegree || prm->cheb_lanczos < 0 ||
+       prm->cheb_lanczos == 1 || prm->cheb_lanczos > kMaxLanczos || !(prm->cheb_ratio == 0.0 || prm->cheb_ratio > 1.0) ||
+       !(prm->cheb_margin == 0.0 || prm->cheb_margin >= 1.0))) {
+    dg_set_error("Chebyshev parameters: degree 0..64, lanczos 0 or 2..64, ratio 0 or > 1, margin 0 or >= 1");
     return DG_ERR_ARG;
   }
   if (!(prm->rtol > 0) || prm->maxit < 1 || (mode == DG_SOLVE_IR_F32 && (!(prm->inner_rtol > 0) || prm->max_outer < 1))) {

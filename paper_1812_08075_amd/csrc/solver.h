@@ -57,6 +57,22 @@ hipError_t blas_copy(const void* a, void* b, int prec, int64_t n, hipStream_t s)
 hipError_t blas_accumulate(double* x, float* xl, int64_t n, hipStream_t s);
 hipError_t blas_zero(void* a, int prec, int64_t n, hipStream_t s);
 hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s);
+// b = a widened to FP64.
+hipError_t blas_widen(const float* a, double* b, int64_t n, hipStream_t s);
+// r -= alpha q (FP64), r.r reduced with `op`, and r32 = r rounded to FP32.
+hipError_t blas_r_update_round(double* r, const double* q, float* r32, int64_t n, double* partial, CgState* st,
+                               int op, hipStream_t s);
+// x += alpha p, p = z + beta p with z in FP32 (x, p FP64).
+hipError_t blas_xp_update_mixed(double* x, double* p, const float* z, int64_t n, CgState* st, hipStream_t s);
+// One Chebyshev step without preconditioner (k_cheb_plain): w = r - t,
+// d = c1 d + c2 w, z += d; the first step has t = d = z = 0; with rd (FP64
+// right-hand side, read instead of r) the last step writes the partial sums of
+// rd.z (blas_cheb_blocks(n) entries) and does not store d.
+hipError_t blas_cheb_step(int prec, const void* r, const double* rd, const void* t, void* d, void* z, double c1,
+                          double c2, bool first, bool last, int64_t n, double* partial, hipStream_t s);
+int64_t blas_cheb_blocks(int64_t n);
+// hist[2j] = alpha, hist[2j+1] = beta of the state.
+hipError_t blas_record(const CgState* st, double* hist, int j, hipStream_t s);
 // every field zero (a fresh state record).
 hipError_t blas_state_zero(CgState* st, hipStream_t s);
 // rr = rr0 = nrm2, alpha = beta = 0.

@@ -131,3 +131,12 @@ def test_binding_rejects_bad_tensors(dg):
         dg._prec_of(torch.zeros(4, dtype=torch.float16))
     with pytest.raises(TypeError):
         dg._vec(np.zeros(16), 16, dg.DG_F64, "x")
+
+
+def test_solve_info_layout_matches_header(dg):
+    """The ctypes mirror of dg_solve_info has the header's fields in order."""
+    text = open(os.path.join(ROOT, "include", "dg.h")).read()
+    body = re.search(r"typedef struct \{([^}]*)\} dg_solve_info;", text).group(1)
+    fields = re.findall(r"^\s*(?:double|int32_t)\s+(\w+);", body, re.M)
+    assert fields == [f for f, _ in dg.dg_solve_info._fields_]
+    assert ctypes.sizeof(dg.dg_solve_info) == 40 and ctypes.sizeof(dg.dg_solve_params) == 56
