@@ -6,7 +6,7 @@
  * Kempf, Hess, Muething, Bastian, "Automatic Code Generation for
  * High-Performance Discontinuous Galerkin Methods on Modern Architectures"):
  * for the linear problems here, the residual without its u-independent
- * terms. Two problems are provided:
+ * terms. The problems:
  *
  *   DG_PROBLEM_DIFFREAC  -div(kappa grad u) + c u, symmetric interior penalty
  *                        (Section 5.2, eq. diffreac_weak), Nitsche terms on
@@ -18,7 +18,15 @@
  *                        at every quadrature point, reaction c (the paper
  *                        uses 10), source f = -6 and Dirichlet data
  *                        g(x) = |x|^2 on the Dirichlet sides; dg_apply is its
- *                        Jacobian action, dg_residual its full residual.
+ *                        Jacobian action, dg_residual its full residual;
+ *   DG_PROBLEM_NONLINEAR -div(kappa(u) grad u) + c u with kappa(u) = 1 + u^2:
+ *                        the same SIPG form with the coefficient evaluated at
+ *                        the solution (kappa on a face from each side's own
+ *                        trace), homogeneous Dirichlet data on the Dirichlet
+ *                        sides; dg_residual is its residual R(u) (the source
+ *                        term is a load vector, dg_load_vector), and
+ *                        dg_apply_jacobian its Jacobian action J(u0) z at a
+ *                        linearization point u0 (Section 2.1).
  *
  * Meshes are structured nx*ny*nz hexahedra of the unit cube, cell
  * e = ex + nx*(ey + ny*ez). Each cell is the image of [0,1]^3 under the
@@ -66,13 +74,15 @@ typedef enum {
   DG_BREAKDOWN = 2          /* dg_solve met p^T A p <= 0 or a non-finite value */
 } dg_status;
 
-enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1, DG_PROBLEM_DIFFREAC_PAPER = 2 };
+enum { DG_PROBLEM_DIFFREAC = 0, DG_PROBLEM_STOKES = 1, DG_PROBLEM_DIFFREAC_PAPER = 2, DG_PROBLEM_NONLINEAR = 3 };
 enum { DG_F64 = 0, DG_F32 = 1 };
 enum { DG_KAPPA_ONE = 0, DG_KAPPA_QP = 1 };
 enum { DG_KAPPA_FACE_TRACE = 0, DG_KAPPA_FACE_ONE = 1 };
 enum { DG_SOLVE_CG_F64 = 0, DG_SOLVE_IR_F32 = 1, DG_SOLVE_RU_F32 = 2, DG_SOLVE_CHEB_F64 = 3,
        DG_SOLVE_CHEB_F32 = 4 };
 enum { DG_PRECOND_NONE = 0, DG_PRECOND_BLOCK_JACOBI = 1 };
+enum { DG_VARIANT_MATRIX_CORE = 0, DG_VARIANT_LINES = 1 };
+enum { DG_TUNE_MAX = 16 };
 
 /* Mesh and operator description (all fields are read by dg_mesh_create). */
 typedef struct {
@@ -134,6 +144,15 @@ typedef struct {
   int32_t pad;
   double lambda_max;        /* CHEB: the largest Ritz value of the estimate (of P A, or of A) */
 } dg_solve_info;
+
+/* Result of dg_mesh_tune: the candidates timed, in order, and the one chosen. */
+typedef struct {
+  int32_t ncand;                 /* candidates timed */
+  int32_t chosen;                /* index of the fastest, now in use */
+  int32_t kind[DG_TUNE_MAX];     /* DG_VARIANT_* */
+  int32_t param[DG_TUNE_MAX];    /* MATRIX_CORE: rows per wavefront; LINES: sweep order */
+  double us[DG_TUNE_MAX];        /* median microseconds per apply */
+} dg_tune_result;
 
 /* Checks a descriptor without touching the GPU (Section 2.1 restrictions:
  * cuboid meshes, isotropic degree). DG_OK, DG_ERR_ARG or DG_ERR_UNSUPPORTED. */
@@ -205,6 +224,15 @@ dg_status dg_precond_apply(const dg_mesh* mesh, int precision, const void* r, vo
 dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
                    const dg_solve_params* params, dg_solve_info* info, void* stream);
 
+/* y = J(u0) z: the Jacobian action of DG_PROBLEM_NONLINEAR's residual at the
+ * linearization point u0 in the direction z (Section 2.1; with kappa(u) =
+ * 1 + u^2 it depends on both inputs, which the kernel evaluates in one fused
+ * pass, Section 3.1). J is not symmetric. Diffusion-reaction vector rules;
+ * y must not overlap u0 or z (u0 and z may be the same vector). Other
+ * problems: DG_ERR_UNSUPPORTED (their Jacobian action is dg_apply). Async. */
+dg_status dg_apply_jacobian(const dg_mesh* mesh, int precision, const void* u0, const void* z, void* y,
+                            void* stream);
+
 /* dg_solve without allocating: for callers that cannot allocate device or
  * pinned host memory (code under HIP graph capture, serving loops, harnesses
  * that forbid hipMalloc). Same arguments, checks, results and status codes as
@@ -223,12 +251,39 @@ dg_status dg_solve(const dg_mesh* mesh, int mode, const double* b, double* x, co
 dg_status dg_solve_noalloc(const dg_mesh* mesh, int mode, const double* b, double* x, const void* kappa,
                            const dg_solve_params* params, dg_solve_info* info, void* stream);
 
-/* r = R(u): the full algebraic residual R_i(u) = r(u_h, phi_i) of the
- * problem, u-independent terms included (Section 2.1), for
- * DG_PROBLEM_DIFFREAC_PAPER: eq. diffreac_weak with K = x x^T + I, f = -6 and
- * g = |x|^2, i.e. r = A u - b with b the source and Dirichlet data terms.
+/* r = R(u): the algebraic residual R_i(u) = r(u_h, phi_i) of the problem
+ * (Section 2.1). DG_PROBLEM_DIFFREAC_PAPER: eq. diffreac_weak with
+ * K = x x^T + I, f = -6 and g = |x|^2, u-independent terms included, i.e.
+ * r = A u - b with b the source and Dirichlet data terms.
+ * DG_PROBLEM_NONLINEAR: r = R(u) without the source term (subtract
+ * dg_load_vector's b for -div(kappa(u) grad u) + c u = f).
  * Other problems: DG_ERR_UNSUPPORTED. Same vector rules as dg_apply. Async. */
 dg_status dg_residual(const dg_mesh* mesh, int precision, const void* u, void* r, void* stream);
+
+/* Variant selection for dg_apply (and the solvers' applies) of one precision
+ * on this mesh, the counterpart of Section 4.2's choice among vectorization
+ * strategies (Algorithms 4 and 5 with a measured cost function). The
+ * candidates are:
+ *   DG_VARIANT_MATRIX_CORE, param = rows per wavefront (1, 2, 4, 8, 16): the
+ *     matrix-core kernel (k = 3, kappa = 1, diffusion-reaction), each
+ *     wavefront marching along y over that many rows;
+ *   DG_VARIANT_LINES, param = sweep order (0: each XCD sweeps one region of
+ *     the mesh, 1: linear order): the line kernels (thread per 1D line).
+ * Without a call the cost model's choice is in use: the matrix-core kernel
+ * where it exists, with the most rows (up to 16) that leave at least 4096
+ * wavefronts, and the region sweep. All variants compute the same operator;
+ * the matrix-core variants and the two sweep orders give bitwise the same
+ * results among themselves. The sweep order is shared by both precisions and
+ * by the other line kernels of the mesh (preconditioner, adjoint, load
+ * vector). Not thread-safe against calls using the mesh; synchronizes the
+ * device when a table is replaced. Stokes: DG_ERR_UNSUPPORTED. */
+dg_status dg_mesh_set_variant(dg_mesh* mesh, int precision, int kind, int param);
+
+/* Times every candidate variant of dg_apply for `precision` on this mesh
+ * (median over `trials` of 10 applies each, on internal zero vectors; the
+ * measured autotuning cost function of Section 4.2) and keeps the fastest in
+ * use. Allocates and frees two vectors; synchronous. trials in 1..100. */
+dg_status dg_mesh_tune(dg_mesh* mesh, int precision, int trials, void* stream, dg_tune_result* out);
 
 /* Physical coordinates of the volume quadrature points, nqp x 3 doubles into a
  * HOST buffer (cell-blocked, same order as kappa). */

@@ -23,7 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libdg.so")
 
 DG_OK, DG_ERR_ARG, DG_ERR_UNSUPPORTED, DG_ERR_DEVICE, DG_ERR_ALLOC = 0, -1, -2, -3, -4
 DG_NOT_CONVERGED, DG_BREAKDOWN = 1, 2
-DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES, DG_PROBLEM_DIFFREAC_PAPER = 0, 1, 2
+DG_PROBLEM_DIFFREAC, DG_PROBLEM_STOKES, DG_PROBLEM_DIFFREAC_PAPER, DG_PROBLEM_NONLINEAR = 0, 1, 2, 3
 DG_F64, DG_F32 = 0, 1
 DG_KAPPA_ONE, DG_KAPPA_QP = 0, 1
 DG_KAPPA_FACE_TRACE, DG_KAPPA_FACE_ONE = 0, 1
@@ -67,10 +67,20 @@ class dg_solve_info(ctypes.Structure):
                 ("inner_applies", ctypes.c_int32), ("pad", ctypes.c_int32), ("lambda_max", ctypes.c_double)]
 
 
+DG_VARIANT_MATRIX_CORE, DG_VARIANT_LINES = 0, 1
+DG_TUNE_MAX = 16
+
+
+class dg_tune_result(ctypes.Structure):
+    _fields_ = [("ncand", ctypes.c_int32), ("chosen", ctypes.c_int32),
+                ("kind", ctypes.c_int32 * DG_TUNE_MAX), ("param", ctypes.c_int32 * DG_TUNE_MAX),
+                ("us", ctypes.c_double * DG_TUNE_MAX)]
+
+
 # every symbol include/dg.h declares
 EXPORTS = ("dg_mesh_desc_validate", "dg_mesh_create", "dg_mesh_destroy", "dg_mesh_info", "dg_apply",
            "dg_apply_adjoint", "dg_precond_apply", "dg_solve", "dg_solve_noalloc", "dg_residual", "dg_mesh_qpoints",
-           "dg_load_vector", "dg_last_error")
+           "dg_load_vector", "dg_apply_jacobian", "dg_mesh_set_variant", "dg_mesh_tune", "dg_last_error")
 
 
 def _load():
@@ -93,6 +103,9 @@ def _load():
         "dg_residual": [V, ctypes.c_int, V, V, V],
         "dg_mesh_qpoints": [V, P(ctypes.c_double)],
         "dg_load_vector": [V, ctypes.c_int, V, V, V],
+        "dg_apply_jacobian": [V, ctypes.c_int, V, V, V, V],
+        "dg_mesh_set_variant": [V, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+        "dg_mesh_tune": [V, ctypes.c_int, ctypes.c_int, V, P(dg_tune_result)],
         "dg_last_error": [],
     }
     for name, args in sig.items():
@@ -272,6 +285,25 @@ def dg_residual(mesh, precision, u, r, stream=None):
     n, _ = _sizes(mesh)
     _check(_lib().dg_residual(mesh, precision, _vec(u, n, precision, "u"), _vec(r, n, precision, "r"),
                               _stream(stream)))
+
+
+def dg_apply_jacobian(mesh, precision, u0, z, y, stream=None):
+    n, _ = _sizes(mesh)
+    _check(_lib().dg_apply_jacobian(mesh, precision, _vec(u0, n, precision, "u0"), _vec(z, n, precision, "z"),
+                                    _vec(y, n, precision, "y"), _stream(stream)))
+
+
+def dg_mesh_set_variant(mesh, precision, kind, param):
+    _check(_lib().dg_mesh_set_variant(mesh, precision, kind, param))
+
+
+def dg_mesh_tune(mesh, precision, trials=5, stream=None):
+    """Times the apply variants of this mesh and keeps the fastest; returns
+    [(kind, param, microseconds), ...] and the index chosen."""
+    out = dg_tune_result()
+    _check(_lib().dg_mesh_tune(mesh, precision, trials, _stream(stream), ctypes.byref(out)))
+    cands = [(out.kind[i], out.param[i], out.us[i]) for i in range(out.ncand)]
+    return cands, out.chosen
 
 
 def dg_mesh_qpoints(mesh) -> np.ndarray:

@@ -285,22 +285,33 @@ int xcd_swizzle_host(int b, int G) {
 }  // namespace
 
 bool mfma_apply_supported(const dg_mesh& M, int prec, bool kappa) {
-  return M.p == 4 && prec == DG_F64 && !kappa && M.d_waves != nullptr;
+  return M.p == 4 && prec == DG_F64 && !kappa && M.d_waves[DG_F64] != nullptr && !M.lines_forced[DG_F64];
+}
+
+// Rows per wavefront: the most, up to NYMAX, that still leave at least 4096
+// wavefronts (16 per CU), else one. Longer marches save more loads (8 global
+// loads per 4 cells with the y-neighbours from LDS, against 12 for one row)
+// but fewer, longer wavefronts fill the chip less evenly.
+int mfma_default_rows(int nx, int ny, int nz) {
+  const int nc = (nx + NC - 1) / NC;
+  for (int r = NYMAX; r > 1; r /= 2)
+    if ((int64_t)nc * ((ny + r - 1) / r) * nz >= 4096) return r;
+  return 1;
 }
 
 hipError_t mfma_setup(dg_mesh& M) {
   if (M.p != 4) return hipSuccess;
+  hipError_t e = mfma_build(M, DG_F64, 0);
+  if (e != hipSuccess) return e;
+  return mfma_build(M, DG_F32, 0);
+}
+
+hipError_t mfma_build(dg_mesh& M, int prec, int rows) {
+  if (M.p != 4 || (prec != DG_F64 && prec != DG_F32)) return hipErrorInvalidValue;
   const int nx = M.desc.nx, ny = M.desc.ny, nz = M.desc.nz;
   const int nc = (nx + NC - 1) / NC;
-  // Rows per wavefront: the most, up to NYMAX, that still leave at least 4096
-  // wavefronts (16 per CU), else one. Longer marches save more loads but
-  // fewer, longer wavefronts fill the chip less evenly.
-  int rows = 1;
-  for (int r = NYMAX; r > 1; r /= 2)
-    if ((int64_t)nc * ((ny + r - 1) / r) * nz >= 4096) {
-      rows = r;
-      break;
-    }
+  if (rows <= 0) rows = mfma_default_rows(nx, ny, nz);
+  if (rows > NYMAX) return hipErrorInvalidValue;
   const int nyb = (ny + rows - 1) / rows;
   const int64_t W = (int64_t)nc * nyb * nz;
   if (W > 0x7fffffff / 2) return hipErrorInvalidValue;
@@ -357,22 +368,39 @@ hipError_t mfma_setup(dg_mesh& M) {
     tab[2 * (size_t)b] = order[2 * (size_t)l];
     tab[2 * (size_t)b + 1] = order[2 * (size_t)l + 1];
   }
-  hipError_t e = hipMalloc(&M.d_waves, sizeof(uint32_t) * tab.size());
+  uint32_t* d = nullptr;
+  hipError_t e = hipMalloc(&d, sizeof(uint32_t) * tab.size());
   if (e != hipSuccess) return e;
-  M.nwaves = G;
-  return hipMemcpy(M.d_waves, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
+  e = hipMemcpy(d, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    return e;
+  }
+  // the old table may still be read by work queued on any stream
+  if (M.d_waves[prec]) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      (void)hipFree(d);
+      return e;
+    }
+    (void)hipFree(M.d_waves[prec]);
+  }
+  M.d_waves[prec] = d;
+  M.nwaves[prec] = G;
+  M.mfma_rows[prec] = rows;
+  return hipSuccess;
 }
 
 hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, double* partial, hipStream_t s) {
   if (M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
-  const int64_t G = M.nwaves;
+  const int64_t G = M.nwaves[DG_F64];
   if (G < 1) return hipSuccess;
   if (partial)
     hipLaunchKernelGGL(k_apply_q3_mfma_dot, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                       (const uint32_t*)M.d_waves, partial);
+                       (const uint32_t*)M.d_waves[DG_F64], partial);
   else
     hipLaunchKernelGGL(k_apply_q3_mfma, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                       (const uint32_t*)M.d_waves);
+                       (const uint32_t*)M.d_waves[DG_F64]);
   return hipGetLastError();
 }
 

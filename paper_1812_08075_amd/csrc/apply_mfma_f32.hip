@@ -262,20 +262,20 @@ __global__ void __launch_bounds__(64)
 }  // namespace
 
 bool mfma_apply_f32_supported(const dg_mesh& M, int prec, bool kappa) {
-  return M.p == 4 && prec == DG_F32 && !kappa && M.d_waves != nullptr;
+  return M.p == 4 && prec == DG_F32 && !kappa && M.d_waves[DG_F32] != nullptr && !M.lines_forced[DG_F32];
 }
 
 hipError_t mfma_apply_f32(const dg_mesh& M, int variant, const float* x, float* y, double* partial,
                           hipStream_t s) {
   if (M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
-  const int64_t G = M.nwaves;
+  const int64_t G = M.nwaves[DG_F32];
   if (G < 1) return hipSuccess;
   if (partial)
     hipLaunchKernelGGL(k_apply_q3_mfma_f32_dot, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                       (const uint32_t*)M.d_waves, partial);
+                       (const uint32_t*)M.d_waves[DG_F32], partial);
   else
     hipLaunchKernelGGL(k_apply_q3_mfma_f32, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
-                       (const uint32_t*)M.d_waves);
+                       (const uint32_t*)M.d_waves[DG_F32]);
   return hipGetLastError();
 }
 

@@ -53,7 +53,8 @@ void validate(const dg_mesh_desc* d) {
   if (!d) fail(DG_ERR_ARG, "desc is NULL");
   if (d->nx < 1 || d->ny < 1 || d->nz < 1) fail(DG_ERR_ARG, "nx, ny, nz must be >= 1");
   if (d->nx > 65535 || d->ny > 65535 || d->nz > 65535) fail(DG_ERR_ARG, "nx, ny, nz must be <= 65535");
-  if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES && d->problem != DG_PROBLEM_DIFFREAC_PAPER)
+  if (d->problem != DG_PROBLEM_DIFFREAC && d->problem != DG_PROBLEM_STOKES && d->problem != DG_PROBLEM_DIFFREAC_PAPER &&
+      d->problem != DG_PROBLEM_NONLINEAR)
     fail(DG_ERR_ARG, "unknown problem");
   if (d->k < 1) fail(DG_ERR_ARG, "k must be >= 1");
   if (d->m < 0) fail(DG_ERR_ARG, "m must be >= 0");
@@ -70,10 +71,13 @@ void validate(const dg_mesh_desc* d) {
   if (d->k + 1 > dgi::PMAX) fail(DG_ERR_UNSUPPORTED, "degree k > 7 is not built");
   if (quad_points(*d) != d->k + 1)
     fail(DG_ERR_UNSUPPORTED, "only m = k + 1 (collocated Gauss-Legendre basis) is built");
-  if (d->problem == DG_PROBLEM_DIFFREAC || d->problem == DG_PROBLEM_DIFFREAC_PAPER) {
+  if (d->problem == DG_PROBLEM_DIFFREAC || d->problem == DG_PROBLEM_DIFFREAC_PAPER ||
+      d->problem == DG_PROBLEM_NONLINEAR) {
     if (d->vertices) fail(DG_ERR_UNSUPPORTED, "diffusion-reaction runs on the regular (axis-aligned) grid only");
     if (d->problem == DG_PROBLEM_DIFFREAC_PAPER && d->kappa_mode != DG_KAPPA_ONE)
       fail(DG_ERR_ARG, "the paper's problem has its own coefficient tensor: kappa_mode must be DG_KAPPA_ONE");
+    if (d->problem == DG_PROBLEM_NONLINEAR && d->kappa_mode != DG_KAPPA_ONE)
+      fail(DG_ERR_ARG, "the nonlinear problem's coefficient is kappa(u): kappa_mode must be DG_KAPPA_ONE");
   } else {
     if (d->k < 2) fail(DG_ERR_UNSUPPORTED, "Stokes needs k >= 2");
     if (d->kappa_mode != DG_KAPPA_ONE) fail(DG_ERR_ARG, "Stokes has no kappa");
@@ -556,7 +560,8 @@ dg_status dg_mesh_destroy(dg_mesh* M) {
     if (M->d_pd) (void)hipFree(M->d_pd);
     if (M->d_pf) (void)hipFree(M->d_pf);
     if (M->d_blocks) (void)hipFree(M->d_blocks);
-    if (M->d_waves) (void)hipFree(M->d_waves);
+    for (uint32_t* w : M->d_waves)
+      if (w) (void)hipFree(w);
     delete M;
     return DG_OK;
   });
@@ -592,6 +597,16 @@ dg_status dg_mesh_info(const dg_mesh* M, dg_mesh_info_t* out) {
       out->bytes_apply[0] = (double)M->ndofs * (16 + (kap ? 8 : 0));
       out->bytes_apply[1] = (double)M->ndofs * (8 + (kap ? 4 : 0));
       out->bytes_adjoint = (double)M->ndofs * 40;
+    } else if (M->desc.problem == DG_PROBLEM_NONLINEAR) {
+      // Jacobian action per cell: per direction and line, the D contractions
+      // of u0 and z (4p^2), the pointwise flux (6p), D^T (2p^2), and at both
+      // ends the own and neighbour traces and normal derivatives of both
+      // inputs (16p), the flux (~20) and the test rows (4p); mass 3p^3
+      const double line = 6 * p * p + 6 * p + 2 * (20 * p + 20);
+      out->flops_apply = E * (3 * p * p * line + 3 * p * p * p + 2 * p * p * p);
+      out->flops_adjoint = 0;
+      out->bytes_apply[0] = (double)M->ndofs * 24;  // read u0 and z, write y
+      out->bytes_apply[1] = (double)M->ndofs * 12;
     } else if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER) {
       // per cell: three forward and three transposed contractions (12 p^4),
       // K(x) grad u and the mass term per point (~25 p^3), and per direction
@@ -642,8 +657,27 @@ dg_status dg_apply(const dg_mesh* M, int precision, const void* x, void* y, cons
       hip_check(dgi::tensor_apply(*M, precision, x, y, false, false, as_stream(stream)), "apply launch");
       return DG_OK;
     }
+    if (M->desc.problem == DG_PROBLEM_NONLINEAR)
+      fail(DG_ERR_UNSUPPORTED, "the nonlinear operator's Jacobian needs a linearization point: dg_apply_jacobian");
     hip_check(dgi::scalar_apply(*M, precision, x, y, kap ? kappa : nullptr, false, as_stream(stream)),
               "apply launch");
+    return DG_OK;
+  });
+}
+
+dg_status dg_apply_jacobian(const dg_mesh* M, int precision, const void* u0, const void* z, void* y, void* stream) {
+  return guarded([&] {
+    check_align({{u0, "u0"}, {z, "z"}, {y, "y"}});
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    check_prec(precision);
+    check_vec(u0, "u0");
+    check_vec(z, "z");
+    check_vec(y, "y");
+    const size_t nb = (size_t)M->ndofs * elem_size(precision);
+    if (overlap(u0, nb, y, nb) || overlap(z, nb, y, nb)) fail(DG_ERR_ARG, "y overlaps u0 or z");
+    if (M->desc.problem != DG_PROBLEM_NONLINEAR)
+      fail(DG_ERR_UNSUPPORTED, "dg_apply_jacobian is for DG_PROBLEM_NONLINEAR (the linear problems: dg_apply)");
+    hip_check(dgi::nonlinear_apply(*M, precision, u0, z, y, true, as_stream(stream)), "Jacobian launch");
     return DG_OK;
   });
 }
@@ -658,7 +692,7 @@ dg_status dg_precond_apply(const dg_mesh* M, int precision, const void* r, void*
     check_vec(z, "z");
     const size_t nb = (size_t)M->ndofs * es;
     if (overlap(r, nb, z, nb)) fail(DG_ERR_ARG, "r and z overlap");
-    if (!dgi::block_jacobi_supported(*M))
+    if (M->desc.problem != DG_PROBLEM_DIFFREAC || !dgi::block_jacobi_supported(*M))
       fail(DG_ERR_UNSUPPORTED,
            "the block-Jacobi preconditioner is built for diffusion-reaction with kappa = 1 and theta = -1");
     hip_check(dgi::block_jacobi(*M, precision, r, z, nullptr, as_stream(stream)), "preconditioner launch");
@@ -715,8 +749,13 @@ dg_status dg_residual(const dg_mesh* M, int precision, const void* u, void* r, v
     check_vec(r, "r");
     const size_t nb = (size_t)M->ndofs * elem_size(precision);
     if (overlap(u, nb, r, nb)) fail(DG_ERR_ARG, "u and r overlap");
+    if (M->desc.problem == DG_PROBLEM_NONLINEAR) {
+      hip_check(dgi::nonlinear_apply(*M, precision, u, u, r, false, as_stream(stream)), "residual launch");
+      return DG_OK;
+    }
     if (M->desc.problem != DG_PROBLEM_DIFFREAC_PAPER)
-      fail(DG_ERR_UNSUPPORTED, "dg_residual needs a problem with its data (DG_PROBLEM_DIFFREAC_PAPER)");
+      fail(DG_ERR_UNSUPPORTED,
+           "dg_residual is for DG_PROBLEM_DIFFREAC_PAPER (with its data) and DG_PROBLEM_NONLINEAR");
     hip_check(dgi::tensor_apply(*M, precision, u, r, false, true, as_stream(stream)), "residual launch");
     return DG_OK;
   });
@@ -758,6 +797,140 @@ dg_status dg_load_vector(const dg_mesh* M, int precision, const void* fq, void* 
     check_vec(b, "b");
     if (overlap(fq, (size_t)M->nqp * es, b, (size_t)M->ndofs * es)) fail(DG_ERR_ARG, "fq and b overlap");
     hip_check(dgi::scalar_load(*M, precision, fq, b, as_stream(stream)), "load vector launch");
+    return DG_OK;
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Variant selection (the autotuning counterpart of Section 4.2's choice among
+// vectorization strategies: here among kernels and launch shapes of one
+// operator, scored by measured time).
+
+namespace {
+
+struct Variant {
+  int kind, param;
+};
+
+// Candidates for the apply of precision `prec` on this mesh, the cost
+// model's default first.
+std::vector<Variant> apply_candidates(const dg_mesh& M, int prec) {
+  std::vector<Variant> v;
+  const bool kap = M.desc.kappa_mode == DG_KAPPA_QP;
+  const bool mc = M.desc.problem == DG_PROBLEM_DIFFREAC && M.p == 4 && !kap && M.d_waves[prec] != nullptr;
+  if (mc) {
+    const int r0 = dgi::mfma_default_rows(M.desc.nx, M.desc.ny, M.desc.nz);
+    v.push_back({DG_VARIANT_MATRIX_CORE, r0});
+    for (int r = 1; r <= 16; r *= 2)
+      if (r != r0 && r <= M.desc.ny) v.push_back({DG_VARIANT_MATRIX_CORE, r});
+  }
+  v.push_back({DG_VARIANT_LINES, 0});
+  v.push_back({DG_VARIANT_LINES, 1});
+  return v;
+}
+
+void set_variant(dg_mesh& M, int prec, const Variant& v) {
+  if (v.kind == DG_VARIANT_MATRIX_CORE) {
+    if (M.mfma_rows[prec] != v.param) hip_check(dgi::mfma_build(M, prec, v.param), "wavefront table");
+    M.lines_forced[prec] = false;
+  } else {
+    M.lines_forced[prec] = M.d_waves[prec] != nullptr;
+    if (M.sweep_linear != v.param) hip_check(dgi::line_sweep_set(M, v.param), "block table");
+  }
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+struct Events {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~Events() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+dg_status dg_mesh_set_variant(dg_mesh* M, int precision, int kind, int param) {
+  return guarded([&] {
+    if (!M) fail(DG_ERR_ARG, "mesh is NULL");
+    check_prec(precision);
+    if (M->desc.problem == DG_PROBLEM_STOKES) fail(DG_ERR_UNSUPPORTED, "the Stokes operator has one variant");
+    const std::vector<Variant> c = apply_candidates(*M, precision);
+    bool ok = false;
+    for (const Variant& v : c) ok = ok || (v.kind == kind && (v.param == param || kind == DG_VARIANT_MATRIX_CORE));
+    if (kind == DG_VARIANT_MATRIX_CORE && !(param >= 1 && param <= 16 && (param & (param - 1)) == 0)) ok = false;
+    if (!ok) fail(DG_ERR_ARG, "no such variant for this mesh and precision");
+    set_variant(*M, precision, {kind, param});
+    return DG_OK;
+  });
+}
+
+dg_status dg_mesh_tune(dg_mesh* M, int precision, int trials, void* stream, dg_tune_result* out) {
+  return guarded([&] {
+    if (!M || !out) fail(DG_ERR_ARG, "mesh and out must not be NULL");
+    check_prec(precision);
+    if (trials < 1 || trials > 100) fail(DG_ERR_ARG, "trials must be in 1..100");
+    if (M->desc.problem == DG_PROBLEM_STOKES) fail(DG_ERR_UNSUPPORTED, "the Stokes operator has one variant");
+    std::memset(out, 0, sizeof(*out));
+    const std::vector<Variant> c = apply_candidates(*M, precision);
+    if ((int)c.size() > DG_TUNE_MAX) fail(DG_ERR_UNSUPPORTED, "too many candidates");
+    const hipStream_t s = as_stream(stream);
+    const size_t es = elem_size(precision);
+    const bool kap = M->desc.kappa_mode == DG_KAPPA_QP;
+    DevBuf x, y, k;
+    if (hipMalloc(&x.p, (size_t)M->ndofs * es) != hipSuccess || hipMalloc(&y.p, (size_t)M->ndofs * es) != hipSuccess ||
+        (kap && hipMalloc(&k.p, (size_t)M->nqp * es) != hipSuccess)) {
+      (void)hipGetLastError();
+      fail(DG_ERR_ALLOC, "device allocation failed (tuning vectors)");
+    }
+    hip_check(hipMemsetAsync(x.p, 0, (size_t)M->ndofs * es, s), "hipMemsetAsync");
+    if (kap) hip_check(hipMemsetAsync(k.p, 0, (size_t)M->nqp * es, s), "hipMemsetAsync");
+    Events ev;
+    hip_check(hipEventCreate(&ev.a), "hipEventCreate");
+    hip_check(hipEventCreate(&ev.b), "hipEventCreate");
+    constexpr int kReps = 10;
+    auto run = [&] {
+      if (M->desc.problem == DG_PROBLEM_DIFFREAC_PAPER)
+        hip_check(dgi::tensor_apply(*M, precision, x.p, y.p, false, false, s), "apply");
+      else if (M->desc.problem == DG_PROBLEM_NONLINEAR)
+        hip_check(dgi::nonlinear_apply(*M, precision, x.p, x.p, y.p, true, s), "Jacobian");
+      else
+        hip_check(dgi::scalar_apply(*M, precision, x.p, y.p, kap ? k.p : nullptr, false, s), "apply");
+    };
+    int best = 0;
+    for (size_t i = 0; i < c.size(); ++i) {
+      set_variant(*M, precision, c[i]);
+      for (int w = 0; w < 3; ++w) run();
+      std::vector<float> t;
+      for (int r = 0; r < trials; ++r) {
+        hip_check(hipEventRecord(ev.a, s), "hipEventRecord");
+        for (int j = 0; j < kReps; ++j) run();
+        hip_check(hipEventRecord(ev.b, s), "hipEventRecord");
+        hip_check(hipEventSynchronize(ev.b), "hipEventSynchronize");
+        float ms = 0.0f;
+        hip_check(hipEventElapsedTime(&ms, ev.a, ev.b), "hipEventElapsedTime");
+        t.push_back(ms);
+      }
+      std::sort(t.begin(), t.end());
+      out->kind[i] = c[i].kind;
+      out->param[i] = c[i].param;
+      out->us[i] = 1e3 * t[t.size() / 2] / kReps;
+      if (out->us[i] < out->us[best]) best = (int)i;
+    }
+    out->ncand = (int)c.size();
+    out->chosen = best;
+    set_variant(*M, precision, c[best]);
+    hip_check(hipStreamSynchronize(s), "hipStreamSynchronize");
     return DG_OK;
   });
 }

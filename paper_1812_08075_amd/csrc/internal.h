@@ -189,8 +189,16 @@ struct dg_mesh {
   dgi::ScalarArgs<double>* d_pd = nullptr;
   dgi::ScalarArgs<float>* d_pf = nullptr;
   uint32_t* d_blocks = nullptr;  // block tables of the apply and adjoint grids (2 words per block)
-  uint32_t* d_waves = nullptr;   // wavefront table of the matrix-core apply (2 words per wavefront)
-  int64_t nwaves = 0;             // its length
+  // wavefront tables of the matrix-core applies (2 words per wavefront), one per
+  // precision [DG_F64, DG_F32], with their lengths and rows per wavefront
+  uint32_t* d_waves[2] = {nullptr, nullptr};
+  int64_t nwaves[2] = {0, 0};
+  int mfma_rows[2] = {0, 0};
+  // variant selection (dg_mesh_set_variant / dg_mesh_tune): the line kernels
+  // serve this precision although a matrix-core kernel exists; order of the
+  // line kernels' block sweep (0: one region per XCD, 1: linear)
+  bool lines_forced[2] = {false, false};
+  int sweep_linear = 0;
   int64_t gamma_off[3] = {0, 0, 0};
 };
 
@@ -235,13 +243,28 @@ hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y,
 bool mfma_apply_f32_supported(const dg_mesh& M, int prec, bool kappa);
 hipError_t mfma_apply_f32(const dg_mesh& M, int variant, const float* x, float* y, double* partial,
                           hipStream_t s);
-// Builds and uploads the wavefront table of the matrix-core apply (M.d_waves).
+// Builds and uploads the wavefront tables of the matrix-core applies
+// (M.d_waves) with the rows per wavefront of the cost model.
 hipError_t mfma_setup(dg_mesh& M);
+// Rebuilds the table of precision slot `prec` with `rows` rows per wavefront
+// (0: the cost model's choice).
+hipError_t mfma_build(dg_mesh& M, int prec, int rows);
+// The cost model's rows per wavefront: the most, up to 16, that leave at
+// least 4096 wavefronts (16 per CU), else 1.
+int mfma_default_rows(int nx, int ny, int nz);
+// Rebuilds the line kernels' block table in the given sweep order (0: one
+// region of the mesh per XCD, 1: linear) and re-uploads the parameter blocks.
+hipError_t line_sweep_set(dg_mesh& M, int linear);
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s);
 // Section 5.2's benchmark operator (K = x x^T + I per point): y = A x (the
 // Jacobian action), or with `residual` y = A x - b with its f and g terms.
 hipError_t tensor_apply(const dg_mesh& M, int prec, const void* x, void* y, bool transpose, bool residual,
                         hipStream_t s);
+
+// The nonlinear diffusion operator (kappa(u) = 1 + u^2): y = J(u0) z (jac)
+// or y = R(u0) (z ignored).
+hipError_t nonlinear_apply(const dg_mesh& M, int prec, const void* u0, const void* z, void* y, bool jac,
+                           hipStream_t s);
 
 // Vector kernels of the solvers (deterministic fixed-order reductions).
 hipError_t blas_dot_partial(const void* a, const void* b, int prec, int64_t n, double* partial,

@@ -47,6 +47,14 @@ __device__ __forceinline__ BlockCoord block_coord(const uint32_t* __restrict__ b
   return c;
 }
 
+// Position of a block's chunk in the plain order (x chunks, then y, then z):
+// where the block writes its partial sums, so that a reduction adds them in
+// the same order whatever sweep order ran the blocks.
+template <typename A>
+__device__ __forceinline__ int64_t chunk_slot(const BlockCoord& bc, const A& a, int eb) {
+  return ((int64_t)bc.ez * a.n[1] + bc.ey) * a.nchunk + bc.ex0 / eb;
+}
+
 // Copies the calling thread's share of its cell into the padded LDS layout:
 // the thread that owns the lines (ta, tb) of cell le moves the P nodes
 // (ta, tb, 0..P-1), one z-plane apart. Per load the lanes of a cell read one

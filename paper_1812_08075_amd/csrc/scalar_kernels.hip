@@ -409,7 +409,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
       __syncthreads();
     }
-    if (threadIdx.x == 0) partial[blockIdx.x] = sh[0];
+    if (threadIdx.x == 0) partial[chunk_slot(bc, a, EB)] = sh[0];
   }
 }
 
@@ -731,9 +731,9 @@ __device__ __forceinline__ void fdm_solve(const ScalarArgs<T>& a, T* sc, const T
 }
 
 // Fixed-order tree sum of one value per thread over the block (NT threads,
-// NT in [128, 256]) into out[blockIdx.x]; sh: 256 doubles of LDS.
+// NT in [128, 256]) into out[slot]; sh: 256 doubles of LDS.
 template <int NT>
-__device__ __forceinline__ void block_sum_to(double val, double* sh, double* out) {
+__device__ __forceinline__ void block_sum_to(double val, double* sh, double* out, int64_t slot) {
   if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
   sh[threadIdx.x] = val;
   __syncthreads();
@@ -742,7 +742,7 @@ __device__ __forceinline__ void block_sum_to(double val, double* sh, double* out
     if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
     __syncthreads();
   }
-  if (threadIdx.x == 0) out[blockIdx.x] = sh[0];
+  if (threadIdx.x == 0) out[slot] = sh[0];
   __syncthreads();
 }
 
@@ -800,8 +800,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     }
   }
   // block sums: r.z, then r.r
-  if (partial) block_sum_to<NT>(rz, sh, partial);
-  if (q) block_sum_to<NT>(rr, sh, partial_rr);
+  if (partial) block_sum_to<NT>(rz, sh, partial, chunk_slot(bc, a, EB));
+  if (q) block_sum_to<NT>(rr, sh, partial_rr, chunk_slot(bc, a, EB));
 }
 
 // One step of the Chebyshev iteration for B z = rhs preconditioned by the
@@ -856,7 +856,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       if (last && rd) rz = fma(rd[i], (double)zi, rz);
     }
   }
-  if (last && rd) block_sum_to<NT>(rz, sh, partial);
+  if (last && rd) block_sum_to<NT>(rz, sh, partial, chunk_slot(bc, a, EB));
 }
 
 // b_i = w_i |J| f_i: with collocation, phi_i(x_q) = delta_iq.
@@ -1037,9 +1037,22 @@ int xcd_swizzle(int b, int G) {
 // split (the sweep front, the region's x-z cross-section, stays small), and
 // inside a region the blocks run y-outermost, then z, then x. Hardware block
 // b runs on XCD b % 8 and takes position swizzle(b) of that order.
-std::vector<uint32_t> block_table(int nx, int ny, int nz, int eb) {
+// linear: the plain order (x chunks, then y, then z) with no XCD renumbering.
+std::vector<uint32_t> block_table(int nx, int ny, int nz, int eb, bool linear) {
   const int nc = (nx + eb - 1) / eb;
   const int G = nc * ny * nz;
+  if (linear) {
+    std::vector<uint32_t> tab(2 * (size_t)G);
+    size_t t = 0;
+    for (int zz = 0; zz < nz; ++zz)
+      for (int yy = 0; yy < ny; ++yy)
+        for (int cc = 0; cc < nc; ++cc) {
+          tab[2 * t] = (uint32_t)(cc * eb) | ((uint32_t)yy << 16);
+          tab[2 * t + 1] = (uint32_t)zz;
+          ++t;
+        }
+    return tab;
+  }
   int best[2] = {1, 1};
   double best_cost = -1;
   for (int rx = 1; rx <= 8; rx *= 2) {
@@ -1109,7 +1122,7 @@ hipError_t scalar_apply(const dg_mesh& M, int prec, const void* x, void* y, cons
 }
 
 int64_t scalar_apply_blocks(const dg_mesh& M, int prec, bool kappa) {
-  if (mfma_apply_supported(M, prec, kappa) || mfma_apply_f32_supported(M, prec, kappa)) return M.nwaves;
+  if (mfma_apply_supported(M, prec, kappa) || mfma_apply_f32_supported(M, prec, kappa)) return M.nwaves[prec];
   return grid_of(M.pd[SP_APPLY]);
 }
 
@@ -1159,11 +1172,18 @@ hipError_t scalar_params_upload(dg_mesh& M) {
   fill_params(M.sd, M.tab, M.p, M.pd);
   fill_params(M.sf, M.tab, M.p, M.pf);
   // block tables: apply grid, then adjoint grid
+  const bool lin = M.sweep_linear != 0;
   const std::vector<uint32_t> ta =
-      block_table(M.pd[SP_APPLY].n[0], M.pd[SP_APPLY].n[1], M.pd[SP_APPLY].n[2], apply_cells_per_block(M.p));
+      block_table(M.pd[SP_APPLY].n[0], M.pd[SP_APPLY].n[1], M.pd[SP_APPLY].n[2], apply_cells_per_block(M.p), lin);
   const std::vector<uint32_t> tj =
       block_table(M.pd[SP_ADJOINT].n[0], M.pd[SP_ADJOINT].n[1], M.pd[SP_ADJOINT].n[2],
-                  adjoint_cells_per_block(M.p));
+                  adjoint_cells_per_block(M.p), lin);
+  if (M.d_blocks) {  // a rebuild: the old table may still be read by queued work
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return e;
+    (void)hipFree(M.d_blocks);
+    M.d_blocks = nullptr;
+  }
   hipError_t e = hipMalloc(&M.d_blocks, sizeof(uint32_t) * (ta.size() + tj.size()));
   if (e != hipSuccess) return e;
   e = hipMemcpy(M.d_blocks, ta.data(), sizeof(uint32_t) * ta.size(), hipMemcpyHostToDevice);
@@ -1178,6 +1198,11 @@ hipError_t scalar_params_upload(dg_mesh& M) {
   e = hipMemcpy(M.d_pd, M.pd, sizeof(M.pd), hipMemcpyHostToDevice);
   if (e != hipSuccess) return e;
   return hipMemcpy(M.d_pf, M.pf, sizeof(M.pf), hipMemcpyHostToDevice);
+}
+
+hipError_t line_sweep_set(dg_mesh& M, int linear) {
+  M.sweep_linear = linear ? 1 : 0;
+  return scalar_params_upload(M);
 }
 
 }  // namespace dgi
