@@ -267,8 +267,11 @@ dg_status dg_residual(const dg_mesh* mesh, int precision, const void* u, void* r
  *   DG_VARIANT_MATRIX_CORE, param = rows per wavefront (1, 2, 4, 8, 16): the
  *     matrix-core kernel (k = 3, kappa = 1, diffusion-reaction), each
  *     wavefront marching along y over that many rows;
- *   DG_VARIANT_LINES, param = sweep order (0: each XCD sweeps one region of
- *     the mesh, 1: linear order): the line kernels (thread per 1D line).
+ *   DG_VARIANT_LINES, param = sweep order (bit 0; 0: each XCD sweeps one
+ *     region of the mesh, 1: linear order) | 2 for the FP32 line kernel of
+ *     k = 3 with its two contractions on the matrix cores
+ *     (v_mfma_f32_4x4x1_16b_f32, FP32 accumulation; else FP32 VALU): the
+ *     line kernels (thread per 1D line).
  * Without a call the cost model's choice is in use: the matrix-core kernel
  * where it exists, with the most rows (up to 16) that leave at least 4096
  * wavefronts, and the region sweep. All variants compute the same operator;

@@ -828,6 +828,11 @@ std::vector<Variant> apply_candidates(const dg_mesh& M, int prec) {
   }
   v.push_back({DG_VARIANT_LINES, 0});
   v.push_back({DG_VARIANT_LINES, 1});
+  if (prec == DG_F32 && M.p == 4 && M.desc.problem == DG_PROBLEM_DIFFREAC) {
+    // FP32 lines of p = 4 with their contractions on the matrix cores
+    v.push_back({DG_VARIANT_LINES, 2});
+    v.push_back({DG_VARIANT_LINES, 3});
+  }
   return v;
 }
 
@@ -837,7 +842,8 @@ void set_variant(dg_mesh& M, int prec, const Variant& v) {
     M.lines_forced[prec] = false;
   } else {
     M.lines_forced[prec] = M.d_waves[prec] != nullptr;
-    if (M.sweep_linear != v.param) hip_check(dgi::line_sweep_set(M, v.param), "block table");
+    if (prec == DG_F32) M.lines_mfma = (v.param & 2) != 0;
+    if (M.sweep_linear != (v.param & 1)) hip_check(dgi::line_sweep_set(M, v.param & 1), "block table");
   }
 }
 

@@ -199,6 +199,8 @@ struct dg_mesh {
   // line kernels' block sweep (0: one region per XCD, 1: linear)
   bool lines_forced[2] = {false, false};
   int sweep_linear = 0;
+  // FP32 line kernel of p = 4: contractions on the matrix cores (else VALU)
+  bool lines_mfma = false;
   int64_t gamma_off[3] = {0, 0, 0};
 };
 

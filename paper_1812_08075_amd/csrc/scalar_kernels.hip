@@ -65,6 +65,64 @@ struct AdjCellsPerBlock {
   static constexpr int value = (128 / (P * P)) > 0 ? (128 / (P * P)) : 1;
 };
 
+// Face fluxes of the two ends of a d-line (general form): Rv[s] multiplies
+// the trace row of side s, Sd[s] (times fB0) its derivative row.
+template <int P, typename T, bool KAPPA, int DIR>
+__device__ __forceinline__ void face_fluxes(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
+                                            const bool* has_nb, const ScalarArgs<T>& a, T* Rv, T* Sd) {
+  const EvenOdd<T>& dv = a.eo[DIR];
+  // own traces and reference-coordinate derivatives at both ends: side 1 uses
+  // the mirror image of the side-0 rows (the derivative row with a sign). They
+  // are formed exactly as the neighbour across that face forms them (same rows,
+  // same order), so both cells see bitwise the same face values and the
+  // discrete operator stays symmetric in floating point (theta = -1).
+  T uT[2] = {T(0), T(0)}, dT[2] = {T(0), T(0)};
+#pragma unroll
+  for (int j = 0; j < P; ++j) {
+    uT[0] = fma(a.e[0][j], v[j], uT[0]);
+    dT[0] = fma(a.de[0][j], v[j], dT[0]);
+    uT[1] = fma(a.e[0][P - 1 - j], v[j], uT[1]);
+    dT[1] = fma(a.de[0][P - 1 - j], v[j], dT[1]);
+  }
+  // (outward normal derivative = -(1/h) dT; the -1/h sits in fAh)
+  const bool face_kappa = KAPPA && !a.kappa_face_one;
+  T kT[2] = {T(1), T(1)};
+  if (face_kappa) {
+    kT[0] = kT[1] = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      kT[0] = fma(a.e[0][j], kv[j], kT[0]);
+      kT[1] = fma(a.e[0][P - 1 - j], kv[j], kT[1]);
+    }
+  }
+  // face fluxes: Rv multiplies the trace row of side s, Sd (times fB0) its derivative row
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
+    // the neighbour across side s meets it with its own side 1-s: trace row
+    // e0 mirrored for s = 0, e0 for s = 1; derivative row likewise (no branch:
+    // the neighbour line is zero where there is none)
+    T uN = T(0), dN = T(0), kN = T(1);
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const int r = s == 0 ? P - 1 - j : j;
+      uN = fma(a.e[0][r], nb[s][j], uN);
+      dN = fma(a.de[0][r], nb[s][j], dN);
+    }
+    if (face_kappa) {
+      kN = T(0);
+#pragma unroll
+      for (int j = 0; j < P; ++j) kN = fma(a.e[0][s == 0 ? P - 1 - j : j], nk[s][j], kN);
+    }
+    // interior: averages and jumps; Dirichlet: the one-sided terms count twice
+    const T sel = has_nb[s] ? T(1) : (dirichlet ? T(2) : T(0));
+    const T g = (has_nb[s] || dirichlet) ? dv.fG : T(0);
+    const T jump = uT[s] - uN;
+    Rv[s] = fma(sel * dv.fAh, kT[s] * dT[s] - kN * dN, g * jump);
+    Sd[s] = sel * (kT[s] * jump);
+  }
+}
+
 // Volume and face work of one 1D line of one cell in direction DIR, without
 // the line's tangential quadrature weight w_a w_b, which the caller applies once.
 //  v, kv: the line's values and kappa at its nodes; nb[s], nk[s]: the
@@ -147,57 +205,8 @@ __device__ __forceinline__ void line_apply(const T* v, const T* kv, const T (*nb
 #pragma unroll
     for (int q = 0; q < H; ++q) om = fma(a.G2c[q], ro[q], om);
   }
-  // own traces and reference-coordinate derivatives at both ends: side 1 uses
-  // the mirror image of the side-0 rows (the derivative row with a sign). They
-  // are formed exactly as the neighbour across that face forms them (same rows,
-  // same order), so both cells see bitwise the same face values and the
-  // discrete operator stays symmetric in floating point (theta = -1).
-  T uT[2] = {T(0), T(0)}, dT[2] = {T(0), T(0)};
-#pragma unroll
-  for (int j = 0; j < P; ++j) {
-    uT[0] = fma(a.e[0][j], v[j], uT[0]);
-    dT[0] = fma(a.de[0][j], v[j], dT[0]);
-    uT[1] = fma(a.e[0][P - 1 - j], v[j], uT[1]);
-    dT[1] = fma(a.de[0][P - 1 - j], v[j], dT[1]);
-  }
-  // (outward normal derivative = -(1/h) dT; the -1/h sits in fAh)
-  const bool face_kappa = KAPPA && !a.kappa_face_one;
-  T kT[2] = {T(1), T(1)};
-  if (face_kappa) {
-    kT[0] = kT[1] = T(0);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      kT[0] = fma(a.e[0][j], kv[j], kT[0]);
-      kT[1] = fma(a.e[0][P - 1 - j], kv[j], kT[1]);
-    }
-  }
-  // face fluxes: Rv multiplies the trace row of side s, Sd (times fB0) its derivative row
   T Rv[2], Sd[2];
-#pragma unroll
-  for (int s = 0; s < 2; ++s) {
-    const bool dirichlet = (a.mask >> (2 * DIR + s)) & 1u;
-    // the neighbour across side s meets it with its own side 1-s: trace row
-    // e0 mirrored for s = 0, e0 for s = 1; derivative row likewise (no branch:
-    // the neighbour line is zero where there is none)
-    T uN = T(0), dN = T(0), kN = T(1);
-#pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const int r = s == 0 ? P - 1 - j : j;
-      uN = fma(a.e[0][r], nb[s][j], uN);
-      dN = fma(a.de[0][r], nb[s][j], dN);
-    }
-    if (face_kappa) {
-      kN = T(0);
-#pragma unroll
-      for (int j = 0; j < P; ++j) kN = fma(a.e[0][s == 0 ? P - 1 - j : j], nk[s][j], kN);
-    }
-    // interior: averages and jumps; Dirichlet: the one-sided terms count twice
-    const T sel = has_nb[s] ? T(1) : (dirichlet ? T(2) : T(0));
-    const T g = (has_nb[s] || dirichlet) ? dv.fG : T(0);
-    const T jump = uT[s] - uN;
-    Rv[s] = fma(sel * dv.fAh, kT[s] * dT[s] - kN * dN, g * jump);
-    Sd[s] = sel * (kT[s] * jump);
-  }
+  face_fluxes<P, T, KAPPA, DIR>(v, kv, nb, nk, has_nb, a, Rv, Sd);
   const T cE = Rv[0] + Rv[1], cO = Rv[0] - Rv[1];
   const T dE = dv.fB0 * (Sd[0] + Sd[1]), dO = dv.fB0 * (Sd[0] - Sd[1]);
 #pragma unroll
@@ -299,14 +308,74 @@ __device__ __forceinline__ void line_apply_const(const T* v, const T (*nb)[P], c
   if (ODD) out[H] = om;
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 lines of p = 4 nodes on the matrix cores: v_mfma_f32_4x4x1_16b_f32
+// computes, for each group of four lanes (a block), the outer product of the
+// A values of its lanes (row i = lane % 4) and the B values (column j =
+// lane % 4) into VGPR i of lane j. With B the lane's own line value k and A
+// the table entry (lane % 4, k), four products accumulate sum_k T[i][k] v_k,
+// i.e. the lane's own line times the 4 x 4 table, node i in VGPR i: a
+// thread-per-line contraction with FP32 products and FP32 accumulation. The
+// caller keeps the control flow uniform (the instruction works on all 64
+// lanes). A[k] holds the lane's table entries, loaded once per thread.
+__device__ __forceinline__ f32x4 mfma_line4(const float* A, const float* v) {
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) acc = __builtin_amdgcn_mfma_f32_4x4x1f32(A[k], v[k], acc, 0, 0, 0);
+  return acc;
+}
+
+// Algorithm 1 on an FP32 line of p = 4 nodes with the two contractions on
+// the matrix cores (the general form of line_apply: D contraction, the
+// quadrature scaling w_q |J| / h_d^2 and pointwise kappa, D^T contraction,
+// mass on the x-lines) and the same face fluxes as line_apply. AD[k] =
+// D[lane % 4][k], ADt[k] = D[k][lane % 4]: the same for every direction.
+template <bool KAPPA, int DIR>
+__device__ __forceinline__ void line_apply_mfma4(const float* v, const float* kv, const float (*nb)[4],
+                                                 const float (*nk)[4], const bool* has_nb,
+                                                 const ScalarArgs<float>& a, bool mass, const float* AD,
+                                                 const float* ADt, float* out) {
+  constexpr int P = 4;
+  const f32x4 d = mfma_line4(AD, v);
+  const float vs = a.vs[DIR];
+  float r[P] = {d.x * (vs * a.w[0]), d.y * (vs * a.w[1]), d.z * (vs * a.w[2]), d.w * (vs * a.w[3])};
+  if (KAPPA) {
+#pragma unroll
+    for (int q = 0; q < P; ++q) r[q] *= kv[q];
+  }
+  const f32x4 o = mfma_line4(ADt, r);
+  out[0] = o.x;
+  out[1] = o.y;
+  out[2] = o.z;
+  out[3] = o.w;
+  if (mass) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) out[i] = fma(a.cw[i], v[i], out[i]);
+  }
+  float Rv[2], Sd[2];
+  face_fluxes<P, float, KAPPA, DIR>(v, kv, nb, nk, has_nb, a, Rv, Sd);
+  const float fB0 = a.eo[DIR].fB0;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    const float t = fma(Rv[0], a.e[0][i], Rv[1] * a.e[0][P - 1 - i]);
+    out[i] += fma(fB0 * Sd[0], a.de[0][i], fma(fB0 * Sd[1], a.de[0][P - 1 - i], t));
+  }
+}
+
 // The line work of direction DIR: line operators for kappa = 1 in FP64, the
 // general form otherwise (FP32 keeps the form whose face values are bitwise
-// the same on both sides of a face).
-template <int P, typename T, bool KAPPA, int DIR>
+// the same on both sides of a face); MC: FP32 lines of p = 4 with the
+// contractions on the matrix cores.
+template <int P, typename T, bool KAPPA, int DIR, bool MC>
 __device__ __forceinline__ void line_work(const T* v, const T* kv, const T (*nb)[P], const T (*nk)[P],
-                                          const bool* has_nb, const ScalarArgs<T>& a, bool mass, T* out) {
+                                          const bool* has_nb, const ScalarArgs<T>& a, bool mass, const T* AD,
+                                          const T* ADt, T* out) {
   if constexpr (!KAPPA && sizeof(T) == 8) {
     line_apply_const<P, T, DIR>(v, nb, has_nb, a, out);
+  } else if constexpr (MC) {
+    static_assert(P == 4 && sizeof(T) == 4, "matrix-core lines: FP32, p = 4");
+    line_apply_mfma4<KAPPA, DIR>(v, kv, nb, nk, has_nb, a, mass, AD, ADt, out);
   } else {
     line_apply<P, T, KAPPA, DIR>(v, kv, nb, nk, has_nb, a, mass, out);
   }
@@ -314,7 +383,7 @@ __device__ __forceinline__ void line_work(const T* v, const T* kv, const T (*nb)
 
 // DOT: every block also writes the sum of x_i y_i over its cells (FP64, fixed
 // order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
-template <int P, typename T, bool KAPPA, bool DOT>
+template <int P, typename T, bool KAPPA, bool DOT, bool MC>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
                    const ScalarArgs<T>* __restrict__ ap, double* __restrict__ partial) {
@@ -351,40 +420,61 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const T wt = a.wl[li];  // tangential weight w_ta w_tb of this thread's lines
   const T* sxe = sx + le * Ly::NP;
   const T* ske = KAPPA ? sk + le * Ly::NP : nullptr;
+  // With the matrix cores every lane runs the line work (the instruction
+  // works on all 64 lanes, so it must not sit in divergent code); a lane of
+  // a cell beyond the row (EB > nvalid) then works on its LDS slots and zero
+  // neighbour lines, reads nothing from global memory and stores nothing.
+  const bool work = MC || active;
+  T AD[MC ? 4 : 1], ADt[MC ? 4 : 1];  // the lane's A operands of the two contractions
+  if (MC) {
+    const int r = threadIdx.x & 3;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      AD[k] = a.D[r * 4 + k];
+      ADt[k] = a.D[k * 4 + r];
+    }
+  }
   T out0[P], out1[P], out2[P];
-  if (active) {
+  if (work) {
     T v[P], kv[P];
     T nb[2][P], nk[2][P];
     bool has[2];
     // lines along x: (i1, i2) = (ta, tb)
     lds_line<P, T, 0>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 0>(ske, ta, tb, kv);
-    neighbor_lines<P, T, 0>(sx, x, e, le, nvalid, ex, nx, 1u, ta, tb, nb, has);
-    if (KAPPA) neighbor_lines<P, T, 0>(sk, kappa, e, le, nvalid, ex, nx, 1u, ta, tb, nk, has);
-    line_work<P, T, KAPPA, 0>(v, kv, nb, nk, has, a, true, out0);
+    neighbor_lines<P, T, 0>(sx, x, e, le, nvalid, active ? ex : 0, active ? nx : 1, 1u, ta, tb, nb, has);
+    if (KAPPA) neighbor_lines<P, T, 0>(sk, kappa, e, le, nvalid, active ? ex : 0, active ? nx : 1, 1u, ta, tb, nk, has);
+    line_work<P, T, KAPPA, 0, MC>(v, kv, nb, nk, has, a, true, AD, ADt, out0);
     // lines along y: (i0, i2) = (ta, tb)
     lds_line<P, T, 1>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 1>(ske, ta, tb, kv);
-    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb1, has1);
-    if (KAPPA) neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nk1, has1);
-    line_work<P, T, KAPPA, 1>(v, kv, nb1, nk1, has1, a, false, out1);
+    neighbor_lines<P, T, 1>(sx, x, e, le, nvalid, active ? bc.ey : 0, active ? ny : 1, (uint32_t)nx, ta, tb, nb1, has1);
+    if (KAPPA)
+      neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, active ? bc.ey : 0, active ? ny : 1, (uint32_t)nx, ta, tb, nk1,
+                              has1);
+    line_work<P, T, KAPPA, 1, MC>(v, kv, nb1, nk1, has1, a, false, AD, ADt, out1);
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
+      for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
+    }
   }
   __syncthreads();
-  if (active) {
+  if (work) {
+    if (active) {
 #pragma unroll
-    for (int i = 0; i < P; ++i) {
-      T* yi = sy + le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
-      *yi = fma(wt, out1[i], *yi);
+      for (int i = 0; i < P; ++i) {
+        T* yi = sy + le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
+        *yi = fma(wt, out1[i], *yi);
+      }
     }
     // lines along z: (i0, i1) = (ta, tb), kept in registers
     T v[P], kv[P];
     lds_line<P, T, 2>(sxe, ta, tb, v);
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
-    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nb2, has2);
-    if (KAPPA) neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, bc.ez, nz, nxy, ta, tb, nk2, has2);
-    line_work<P, T, KAPPA, 2>(v, kv, nb2, nk2, has2, a, false, out2);
+    neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, active ? bc.ez : 0, active ? nz : 1, nxy, ta, tb, nb2, has2);
+    if (KAPPA)
+      neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, active ? bc.ez : 0, active ? nz : 1, nxy, ta, tb, nk2, has2);
+    line_work<P, T, KAPPA, 2, MC>(v, kv, nb2, nk2, has2, a, false, AD, ADt, out2);
   }
   __syncthreads();
   double pq = 0.0;
@@ -907,14 +997,26 @@ hipError_t launch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   const ScalarArgs<T>* ap = device_params<T>(M) + variant;
   const dim3 grid((unsigned)G), block(EB * P * P);
+  constexpr bool MCOK = P == 4 && sizeof(T) == 4;  // FP32 lines of p = 4 may use the matrix cores
+  if (MCOK && M.lines_mfma) {
+    if (kappa && partial)
+      hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+    else if (kappa)
+      hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+    else if (partial)
+      hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+    else
+      hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+    return hipGetLastError();
+  }
   if (kappa && partial)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true, true>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
   else if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
   else if (partial)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false, true>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
   else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
   return hipGetLastError();
 }
 

@@ -26,7 +26,10 @@ def test_q3_variants_agree(gpu_lib, prec):
     dt = torch.float64 if prec == 0 else torch.float32
     x = _x(w, n, dt)
     outs = {}
-    for kind, param in [(0, 1), (0, 2), (0, 4), (0, 8), (1, 0), (1, 1)]:
+    cands = [(0, 1), (0, 2), (0, 4), (0, 8), (1, 0), (1, 1)]
+    if prec == 1:  # the FP32 line kernel with its contractions on the matrix cores
+        cands += [(1, 2), (1, 3)]
+    for kind, param in cands:
         dg.dg_mesh_set_variant(mesh.handle, prec, kind, param)
         y = torch.empty_like(x)
         dg.dg_apply(mesh.handle, prec, x, y)
@@ -35,9 +38,14 @@ def test_q3_variants_agree(gpu_lib, prec):
     for r in (2, 4, 8):
         assert np.array_equal(outs[(0, r)], outs[(0, 1)]), r
     assert np.array_equal(outs[(1, 1)], outs[(1, 0)])
+    keys = [(0, 1), (1, 0)]
+    if prec == 1:
+        assert np.array_equal(outs[(1, 3)], outs[(1, 2)])
+        assert not np.array_equal(outs[(1, 2)], outs[(1, 0)])  # FP32 matrix-core products, not VALU
+        keys.append((1, 2))
     ref = ScalarDG(problem_from_workload(w, n=n)).assemble().matvec(x.double().cpu().numpy())
     tol = 1e-12 if prec == 0 else 2e-6
-    for key in ((0, 1), (1, 0)):
+    for key in keys:
         err = np.linalg.norm(outs[key] - ref) / np.linalg.norm(ref)
         print(key, f"{err:.2e}")
         assert err <= tol, (key, err)
@@ -144,3 +152,42 @@ def test_set_variant_rejects(gpu_lib):
     with pytest.raises(dg.DGError) as ei:
         dg.dg_mesh_tune(ms.handle, 0)
     assert ei.value.status == dg.DG_ERR_UNSUPPORTED
+
+
+def test_tune_q3_fp32_candidates(gpu_lib):
+    """FP32 at k = 3: the matrix-core kernel (FP64 products on FP32 vectors),
+    and the line kernel with FP32 VALU or FP32 matrix-core contractions."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[2]
+    mesh = dg.Mesh(dg.desc_from_workload(w, n=16))
+    cands, chosen = dg.dg_mesh_tune(mesh.handle, 1, trials=3)
+    print(cands, chosen)
+    assert [(k, p) for k, p, _ in cands] == [(0, 1), (0, 2), (0, 4), (0, 8), (0, 16), (1, 0), (1, 1), (1, 2), (1, 3)]
+    assert chosen == int(np.argmin([t for _, _, t in cands]))
+
+
+def test_fp32_kappa_lines_on_matrix_cores(gpu_lib):
+    """kappa per point at k = 3 in FP32 runs the line kernel; with its
+    contractions on the matrix cores it stays within FP32 accuracy of the
+    oracle (kappa traces on the faces)."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[4]
+    n = 5
+    desc = dg.desc_from_workload(w, n=n)
+    desc.k = 3
+    desc.m = 0
+    mesh = dg.Mesh(desc)
+    nq = mesh.info.nqp
+    kap = workloads.lognormal(nq, 17)
+    x = workloads.uniform(mesh.ndofs, 18)
+    from oracle import Problem, ScalarDG as SDG
+    ref = SDG(Problem(n, n, n, k=3, kappa=kap)).assemble("explicit").matvec(x)
+    res = {}
+    for param in (0, 2):
+        dg.dg_mesh_set_variant(mesh.handle, 1, 1, param)
+        y = torch.empty(mesh.ndofs, dtype=torch.float32, device="cuda")
+        dg.dg_apply(mesh.handle, 1, torch.from_numpy(x).float().cuda(), y, torch.from_numpy(kap).float().cuda())
+        torch.cuda.synchronize()
+        res[param] = np.linalg.norm(y.double().cpu().numpy() - ref) / np.linalg.norm(ref)
+        print(param, res[param])
+    assert res[0] <= 2e-6 and res[2] <= 2e-6
