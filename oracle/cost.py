@@ -1,4 +1,6 @@
-"""Operation counts used to report GFLOP/s (host-side bookkeeping only)."""
+"""The paper's operation count of one sum-factorization kernel (test infrastructure;
+oracle only): checks the library's flop model, which uses the same count for
+its non-collocated contractions."""
 from __future__ import annotations
 
 

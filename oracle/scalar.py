@@ -219,8 +219,12 @@ class ScalarDG:
                 for s in range(2):
                     nb = mesh.neighbor(e, d, s)
                     if nb >= 0:
-                        col, B = self.block_row(nb)[slot(d, 1 - s)]
-                        assert col == e
+                        # block (row nb, column e) of A: the face shared by e and nb,
+                        # test functions on nb's side, trial functions on e's side
+                        if s == 1:  # e = T^-, nb = T^+
+                            B = self.interior_face_blocks(e, nb, d)[1][0]
+                        else:  # nb = T^-, e = T^+
+                            B = self.interior_face_blocks(nb, e, d)[0][1]
                         out[r] += B.T @ G[nb]
         return out
 

@@ -1,7 +1,7 @@
 """Flop bookkeeping against hand-worked values of eq. sumfactcost."""
 import os
 
-from paper_1812_08075_amd.flops import sumfact_cost
+from oracle.cost import sumfact_cost
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 

@@ -58,18 +58,24 @@ def test_stokes_poiseuille_residual(gpu_lib):
 
 
 def test_stokes_full_size_sampled_rows(gpu_lib):
-    """The 32^3 perturbed Q3/Q2 workload at full size, 40 sampled cells."""
+    """The 32^3 perturbed Q3/Q2 workload at full size, 512 sampled cells
+    (corners, edges, faces, the Neumann side and random interior cells; oracle
+    rows in worker processes), relative L2 and elementwise."""
+    from oracle_pool import rows
     dg = gpu_lib
     w = workloads.WORKLOADS[3]
     print("case: stokes 32^3 sampled rows", flush=True)
     x = workloads.inputs(w, "x")
     mesh, y = gpu_apply(dg, dg.desc_from_workload(w), x)
-    op = StokesDG(problem_from_workload(w))
+    n, E = w.n, w.nelem
     rng = np.random.default_rng(3)
-    cells = np.unique(np.concatenate([rng.choice(w.nelem, 36, replace=False), [0, w.nelem - 1, 31, 32 * 32 * 16]]))
+    fixed = [0, n - 1, n * n - 1, E - 1, E - n, n * (n - 1), 31, 32 * 32 * 16, (n // 2) * (1 + n + n * n)]
+    cells = np.unique(np.concatenate([fixed, rng.choice(E, 520, replace=False)]))[:512]
+    (ref,) = rows("stokes", 3, cells)
     N = w.dofs_per_elem
     got = y.reshape(-1, N)[cells]
-    assert relerr(got, op.apply_rows(x, cells)) < TOL64
+    assert relerr(got, ref) < TOL64
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
 
 
 def test_stokes_deterministic(gpu_lib):
@@ -87,3 +93,18 @@ def test_stokes_fp32_unsupported(gpu_lib):
     x = torch.zeros(mesh.ndofs, dtype=torch.float32, device="cuda")
     with pytest.raises(dg.DGError):
         mesh.apply(x)
+
+
+def test_stokes_flop_model_uses_the_sum_factorization_cost(gpu_lib):
+    """The library's flop model of the Stokes apply counts the pressure
+    interpolation forward and back with the paper's sum-factorization cost
+    (eq. sumfactcost: 888 flops for 4 x 3 per direction)."""
+    from oracle.cost import sumfact_cost
+    dg = gpu_lib
+    w = workloads.WORKLOADS[3].scaled(2)
+    mesh = dg.Mesh(dg.desc_from_workload(w))
+    p, kp, E = w.p, w.k, w.nelem
+    csf = sumfact_cost((p, p, p), (kp, kp, kp))
+    assert csf == 888
+    face = 3 * (10 * p ** 3) + 60 * p * p
+    assert mesh.info.flops_apply == E * (18 * p ** 4 + 2 * csf + 220 * p ** 3 + 6 * face)
