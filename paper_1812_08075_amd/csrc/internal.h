@@ -234,6 +234,15 @@ int64_t block_jacobi_blocks(const dg_mesh& M);
 hipError_t cheb_block_jacobi(const dg_mesh& M, int prec, const void* r, const double* rd, const void* t, void* d,
                              void* z, double c1, double c2, bool first, bool last, double* partial, hipStream_t s);
 inline bool block_jacobi_supported(const dg_mesh& M) { return M.pd[SP_APPLY].fdm_ok != 0; }
+// One step k >= 1 of the Chebyshev iteration in one pass over the cells (the
+// line-kernel apply with the step as its epilogue): t = A z, w = rhs - t
+// (bj: w = P (rhs - t)), d = c1 d + c2 w, zout = z + d; the rhs is rd (FP64,
+// rounded) when given, else r; with rd the last step writes the partial sums
+// of rd.zout (block_jacobi_blocks(M) entries) and does not store d. zout must
+// not alias z. bj requires kappa == NULL.
+hipError_t cheb_apply(const dg_mesh& M, int prec, const void* z, void* zout, const void* kappa, const void* r,
+                      const double* rd, void* d, double c1, double c2, bool last, bool bj, double* partial,
+                      hipStream_t s);
 // Fills M.pd / M.pf from M.sd / M.sf (face constants per variant, sweep grid,
 // line weights) and uploads them to M.d_pd / M.d_pf (allocated by the caller).
 hipError_t scalar_params_upload(dg_mesh& M);

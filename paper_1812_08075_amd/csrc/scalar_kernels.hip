@@ -381,20 +381,175 @@ __device__ __forceinline__ void line_work(const T* v, const T* kv, const T (*nb)
   }
 }
 
+// ---------------------------------------------------------------------------
+// Block-Jacobi preconditioner: z = B_T^-1 r on every cell T, B_T the diagonal
+// block of the operator, by fast diagonalization (tables in
+// ScalarArgs::fdmV, fdmL): the transposed eigenvector contractions along z,
+// y and x, the division by lam_x + lam_y + lam_z on the x-lines, and the
+// eigenvector contractions back along x, y and z. No neighbour data.
+
+// side-type variant 3 t0 + t1 of a cell at position c of n along direction d
+__device__ __forceinline__ int fdm_variant(int c, int n, uint32_t mask, int d) {
+  const int t0 = c > 0 ? 0 : ((mask >> (2 * d)) & 1u ? 1 : 2);
+  const int t1 = c < n - 1 ? 0 : ((mask >> (2 * d + 1)) & 1u ? 1 : 2);
+  return 3 * t0 + t1;
+}
+
+// o = V^T v
+template <int P, typename T>
+__device__ __forceinline__ void fdm_forward(const T* __restrict__ V, const T* v, T* o) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc = fma(V[j * P + i], v[j], acc);
+    o[i] = acc;
+  }
+}
+
+// o = V t
+template <int P, typename T>
+__device__ __forceinline__ void fdm_backward(const T* __restrict__ V, const T* t, T* o) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int j = 0; j < P; ++j) acc = fma(V[i * P + j], t[j], acc);
+    o[i] = acc;
+  }
+}
+
+// The x-line part of one cell with the tables (V, lam) of its x variant:
+// forward, divide by lam_x + lam_y + lam_z, backward.
+template <int P, typename T>
+__device__ __forceinline__ void fdm_x(const T* V, const T* lam, T lyz, T* v) {
+  T o[P];
+  fdm_forward<P, T>(V, v, o);
+#pragma unroll
+  for (int j = 0; j < P; ++j) o[j] = o[j] / (lam[j] + lyz);
+  fdm_backward<P, T>(V, o, v);
+}
+
+// Side-type variants of a block's cells for the preconditioner tables: y and
+// z are block-uniform, x differs for the first and last cells of a row; the
+// block's three possible x tables (its first cell's, the interior one, its
+// last cell's) are staged in LDS.
+struct FdmVariants {
+  int vx, vy, vz, vfirst, vlast;
+};
+
+template <int P, typename T>
+__device__ __forceinline__ FdmVariants fdm_setup(const ScalarArgs<T>& a, const BlockCoord& bc, int nvalid, int le,
+                                                 T* sV, T* sL) {
+  constexpr int L = P * P;
+  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
+  const uint32_t mask = a.mask;
+  FdmVariants v;
+  v.vx = fdm_variant(bc.ex0 + le, nx, mask, 0);
+  // block-uniform (made explicit so that the tables are read with scalar loads)
+  v.vy = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ey, ny, mask, 1));
+  v.vz = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ez, nz, mask, 2));
+  v.vfirst = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0, nx, mask, 0));
+  v.vlast = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0 + nvalid - 1, nx, mask, 0));
+  for (int i = threadIdx.x; i < 3 * (L + P); i += blockDim.x) {
+    const int k = i / (L + P), e = i - k * (L + P);
+    const int u = k == 0 ? v.vfirst : (k == 1 ? 0 : v.vlast);
+    if (e < L) sV[k * L + e] = a.fdmV[0][u][e];
+    else sL[k * P + e - L] = a.fdmL[0][u][e - L];
+  }
+  return v;
+}
+
+// o = B_T^-1 rv for the thread's column (ta, tb, 0..P-1) of its cell, by the
+// five phases of fast diagonalization through the cell's LDS block sc. Every
+// thread of the block calls it (it synchronizes); inactive threads pass
+// active = false.
+template <int P, typename T>
+__device__ __forceinline__ void fdm_solve(const ScalarArgs<T>& a, T* sc, const T* sV, const T* sL,
+                                          const FdmVariants& fv, bool active, int ta, int tb, const T* rv, T* o) {
+  constexpr int L = P * P;
+  T v[P], w[P];
+  if (active) {  // z-lines: the thread's own column
+    fdm_forward<P, T>(a.fdmV[2][fv.vz], rv, w);
+    lds_store_line<P, T, 2>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {  // y-lines (i0, i2) = (ta, tb)
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_forward<P, T>(a.fdmV[1][fv.vy], v, w);
+    lds_store_line<P, T, 1>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {  // x-lines (i1, i2) = (ta, tb), the cell's x tables from LDS
+    lds_line<P, T, 0>(sc, ta, tb, v);
+    const int slot = fv.vx == fv.vfirst ? 0 : (fv.vx == fv.vlast ? 2 : 1);
+    fdm_x<P, T>(sV + slot * L, sL + slot * P, a.fdmL[1][fv.vy][ta] + a.fdmL[2][fv.vz][tb], v);
+    lds_store_line<P, T, 0>(sc, ta, tb, v);
+  }
+  __syncthreads();
+  if (active) {
+    lds_line<P, T, 1>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[1][fv.vy], v, w);
+    lds_store_line<P, T, 1>(sc, ta, tb, w);
+  }
+  __syncthreads();
+  if (active) {
+    lds_line<P, T, 2>(sc, ta, tb, v);
+    fdm_backward<P, T>(a.fdmV[2][fv.vz], v, o);
+  }
+}
+
+// Fixed-order tree sum of one value per thread over the block (NT threads,
+// NT in [128, 256]) into out[slot]; sh: 256 doubles of LDS.
+template <int NT>
+__device__ __forceinline__ void block_sum_to(double val, double* sh, double* out, int64_t slot) {
+  if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
+  sh[threadIdx.x] = val;
+  __syncthreads();
+#pragma unroll
+  for (int st = 128; st > 0; st >>= 1) {
+    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[slot] = sh[0];
+  __syncthreads();
+}
+
+// One step k >= 1 of the Chebyshev iteration fused into the apply (the
+// epilogue of k_scalar_apply with EPI_CHEB / EPI_CHEB_BJ): with t = A z the
+// apply's result, w = rhs - t (EPI_CHEB_BJ: w = P (rhs - t), the block-Jacobi
+// inverse by fast diagonalization on the same cells and threads),
+// d = c1 d + c2 w, and y = z + d (a second vector: neighbours still read z).
+// The right-hand side is rd (FP64, rounded) when given, else r; with rd the
+// last step also reduces rd.y per block and does not store d.
+template <typename T>
+struct ChebStep {
+  const T* r;
+  const double* rd;
+  T* d;
+  T c1, c2;
+  int last;
+};
+
+enum : int { EPI_STORE = 0, EPI_CHEB = 1, EPI_CHEB_BJ = 2 };
+
 // DOT: every block also writes the sum of x_i y_i over its cells (FP64, fixed
 // order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
-template <int P, typename T, bool KAPPA, bool DOT, bool MC>
+// EPI: what happens to the result t = A x of a block's cells (ChebStep).
+template <int P, typename T, bool KAPPA, bool DOT, bool MC, int EPI>
 __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     k_scalar_apply(const T* __restrict__ x, T* __restrict__ y, const T* __restrict__ kappa,
-                   const ScalarArgs<T>* __restrict__ ap, double* __restrict__ partial) {
+                   const ScalarArgs<T>* __restrict__ ap, double* __restrict__ partial, const ChebStep<T> cs) {
   const ScalarArgs<T>& a = *ap;
   constexpr int EB = CellsPerBlock<P>::value;
   constexpr int L = P * P, N = P * P * P, NT = EB * L;
   using Ly = Layout<P>;
   static_assert(EB * Ly::NP * sizeof(T) >= 256 * sizeof(double), "reduction scratch");
+  static_assert(!(EPI == EPI_CHEB_BJ && KAPPA), "the block-Jacobi inverse is built for kappa = 1");
   __shared__ T sx[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
   __shared__ __attribute__((aligned(16))) T sy[EB * Ly::NP];  // x-line results, then += y-line results
+  __shared__ T sV[EPI == EPI_CHEB_BJ ? 3 * L : 1], sL[EPI == EPI_CHEB_BJ ? 3 * P : 1];
 
   const BlockCoord bc = block_coord(a.blocks);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -411,6 +566,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   const uint32_t nxy = (uint32_t)nx * ny;
   T nb1[2][P], nk1[2][P], nb2[2][P], nk2[2][P];
   bool has1[2], has2[2];
+  FdmVariants fv{};
+  if constexpr (EPI == EPI_CHEB_BJ) fv = fdm_setup<P, T>(a, bc, nvalid, le, sV, sL);
   if (active) {
     load_cell_column<P, T>(sx, x, gbase, le, ta, tb);
     if (KAPPA) load_cell_column<P, T>(sk, kappa, gbase, le, ta, tb);
@@ -478,14 +635,54 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   }
   __syncthreads();
   double pq = 0.0;
-  if (active) {
-    const int lo = le * Ly::NP + ta + Ly::S1 * tb;
-    T* __restrict__ ye = y + e * N + ta + P * tb;
+  if constexpr (EPI == EPI_STORE) {
+    if (active) {
+      const int lo = le * Ly::NP + ta + Ly::S1 * tb;
+      T* __restrict__ ye = y + e * N + ta + P * tb;
 #pragma unroll
-    for (int j = 0; j < P; ++j) {
-      const T v = fma(wt, out2[j], sy[lo + j * Ly::S2]);
-      ye[j * L] = v;
-      if (DOT) pq = fma((double)sx[lo + j * Ly::S2], (double)v, pq);
+      for (int j = 0; j < P; ++j) {
+        const T v = fma(wt, out2[j], sy[lo + j * Ly::S2]);
+        ye[j * L] = v;
+        if (DOT) pq = fma((double)sx[lo + j * Ly::S2], (double)v, pq);
+      }
+    }
+  } else {
+    // the Chebyshev step on the thread's column (ta, tb, 0..P-1): it reads its
+    // own column of z from sx before the preconditioner overwrites it there
+    const int lo = le * Ly::NP + ta + Ly::S1 * tb;
+    const size_t col = (size_t)e * N + ta + P * tb;
+    T w[P], zv[P], o[P];
+#pragma unroll
+    for (int j = 0; j < P; ++j) w[j] = zv[j] = T(0);
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const T t = fma(wt, out2[j], sy[lo + j * Ly::S2]);
+        zv[j] = sx[lo + j * Ly::S2];
+        const T ri = cs.rd ? (T)cs.rd[col + (size_t)j * L] : cs.r[col + (size_t)j * L];
+        w[j] = ri - t;
+      }
+    }
+    if constexpr (EPI == EPI_CHEB_BJ) {
+      fdm_solve<P, T>(a, sx + le * Ly::NP, sV, sL, fv, active, ta, tb, w, o);
+    } else {
+#pragma unroll
+      for (int j = 0; j < P; ++j) o[j] = w[j];
+    }
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < P; ++j) {
+        const size_t i = col + (size_t)j * L;
+        const T dj = fma(cs.c1, cs.d[i], cs.c2 * o[j]);
+        const T zj = zv[j] + dj;
+        if (!cs.last) cs.d[i] = dj;
+        y[i] = zj;
+        if (cs.last && cs.rd) pq = fma(cs.rd[i], (double)zj, pq);
+      }
+    }
+    if (cs.last && cs.rd) {
+      __syncthreads();  // sy becomes the reduction scratch
+      block_sum_to<NT>(pq, reinterpret_cast<double*>(sy), partial, chunk_slot(bc, a, EB));
     }
   }
   if (DOT) {  // fixed-order tree over the block (NT in [128, 256]), sy as scratch
@@ -702,140 +899,6 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
   }
 }
 
-// ---------------------------------------------------------------------------
-// Block-Jacobi preconditioner: z = B_T^-1 r on every cell T, B_T the diagonal
-// block of the operator, by fast diagonalization (tables in
-// ScalarArgs::fdmV, fdmL): the transposed eigenvector contractions along z,
-// y and x, the division by lam_x + lam_y + lam_z on the x-lines, and the
-// eigenvector contractions back along x, y and z. No neighbour data.
-
-// side-type variant 3 t0 + t1 of a cell at position c of n along direction d
-__device__ __forceinline__ int fdm_variant(int c, int n, uint32_t mask, int d) {
-  const int t0 = c > 0 ? 0 : ((mask >> (2 * d)) & 1u ? 1 : 2);
-  const int t1 = c < n - 1 ? 0 : ((mask >> (2 * d + 1)) & 1u ? 1 : 2);
-  return 3 * t0 + t1;
-}
-
-// o = V^T v
-template <int P, typename T>
-__device__ __forceinline__ void fdm_forward(const T* __restrict__ V, const T* v, T* o) {
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j < P; ++j) acc = fma(V[j * P + i], v[j], acc);
-    o[i] = acc;
-  }
-}
-
-// o = V t
-template <int P, typename T>
-__device__ __forceinline__ void fdm_backward(const T* __restrict__ V, const T* t, T* o) {
-#pragma unroll
-  for (int i = 0; i < P; ++i) {
-    T acc = T(0);
-#pragma unroll
-    for (int j = 0; j < P; ++j) acc = fma(V[i * P + j], t[j], acc);
-    o[i] = acc;
-  }
-}
-
-// The x-line part of one cell with the tables (V, lam) of its x variant:
-// forward, divide by lam_x + lam_y + lam_z, backward.
-template <int P, typename T>
-__device__ __forceinline__ void fdm_x(const T* V, const T* lam, T lyz, T* v) {
-  T o[P];
-  fdm_forward<P, T>(V, v, o);
-#pragma unroll
-  for (int j = 0; j < P; ++j) o[j] = o[j] / (lam[j] + lyz);
-  fdm_backward<P, T>(V, o, v);
-}
-
-// Side-type variants of a block's cells for the preconditioner tables: y and
-// z are block-uniform, x differs for the first and last cells of a row; the
-// block's three possible x tables (its first cell's, the interior one, its
-// last cell's) are staged in LDS.
-struct FdmVariants {
-  int vx, vy, vz, vfirst, vlast;
-};
-
-template <int P, typename T>
-__device__ __forceinline__ FdmVariants fdm_setup(const ScalarArgs<T>& a, const BlockCoord& bc, int nvalid, int le,
-                                                 T* sV, T* sL) {
-  constexpr int L = P * P;
-  const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
-  const uint32_t mask = a.mask;
-  FdmVariants v;
-  v.vx = fdm_variant(bc.ex0 + le, nx, mask, 0);
-  // block-uniform (made explicit so that the tables are read with scalar loads)
-  v.vy = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ey, ny, mask, 1));
-  v.vz = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ez, nz, mask, 2));
-  v.vfirst = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0, nx, mask, 0));
-  v.vlast = __builtin_amdgcn_readfirstlane(fdm_variant(bc.ex0 + nvalid - 1, nx, mask, 0));
-  for (int i = threadIdx.x; i < 3 * (L + P); i += blockDim.x) {
-    const int k = i / (L + P), e = i - k * (L + P);
-    const int u = k == 0 ? v.vfirst : (k == 1 ? 0 : v.vlast);
-    if (e < L) sV[k * L + e] = a.fdmV[0][u][e];
-    else sL[k * P + e - L] = a.fdmL[0][u][e - L];
-  }
-  return v;
-}
-
-// o = B_T^-1 rv for the thread's column (ta, tb, 0..P-1) of its cell, by the
-// five phases of fast diagonalization through the cell's LDS block sc. Every
-// thread of the block calls it (it synchronizes); inactive threads pass
-// active = false.
-template <int P, typename T>
-__device__ __forceinline__ void fdm_solve(const ScalarArgs<T>& a, T* sc, const T* sV, const T* sL,
-                                          const FdmVariants& fv, bool active, int ta, int tb, const T* rv, T* o) {
-  constexpr int L = P * P;
-  T v[P], w[P];
-  if (active) {  // z-lines: the thread's own column
-    fdm_forward<P, T>(a.fdmV[2][fv.vz], rv, w);
-    lds_store_line<P, T, 2>(sc, ta, tb, w);
-  }
-  __syncthreads();
-  if (active) {  // y-lines (i0, i2) = (ta, tb)
-    lds_line<P, T, 1>(sc, ta, tb, v);
-    fdm_forward<P, T>(a.fdmV[1][fv.vy], v, w);
-    lds_store_line<P, T, 1>(sc, ta, tb, w);
-  }
-  __syncthreads();
-  if (active) {  // x-lines (i1, i2) = (ta, tb), the cell's x tables from LDS
-    lds_line<P, T, 0>(sc, ta, tb, v);
-    const int slot = fv.vx == fv.vfirst ? 0 : (fv.vx == fv.vlast ? 2 : 1);
-    fdm_x<P, T>(sV + slot * L, sL + slot * P, a.fdmL[1][fv.vy][ta] + a.fdmL[2][fv.vz][tb], v);
-    lds_store_line<P, T, 0>(sc, ta, tb, v);
-  }
-  __syncthreads();
-  if (active) {
-    lds_line<P, T, 1>(sc, ta, tb, v);
-    fdm_backward<P, T>(a.fdmV[1][fv.vy], v, w);
-    lds_store_line<P, T, 1>(sc, ta, tb, w);
-  }
-  __syncthreads();
-  if (active) {
-    lds_line<P, T, 2>(sc, ta, tb, v);
-    fdm_backward<P, T>(a.fdmV[2][fv.vz], v, o);
-  }
-}
-
-// Fixed-order tree sum of one value per thread over the block (NT threads,
-// NT in [128, 256]) into out[slot]; sh: 256 doubles of LDS.
-template <int NT>
-__device__ __forceinline__ void block_sum_to(double val, double* sh, double* out, int64_t slot) {
-  if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
-  sh[threadIdx.x] = val;
-  __syncthreads();
-#pragma unroll
-  for (int st = 128; st > 0; st >>= 1) {
-    if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[slot] = sh[0];
-  __syncthreads();
-}
-
 // With q != NULL the residual is first updated in place, r -= alpha q (alpha
 // read from device memory), and partial sums of r.r go to partial_rr: one
 // pass over r, q and z per conjugate-gradient iteration.
@@ -997,27 +1060,73 @@ hipError_t launch_apply(const dg_mesh& M, int variant, const T* x, T* y, const T
   if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
   const ScalarArgs<T>* ap = device_params<T>(M) + variant;
   const dim3 grid((unsigned)G), block(EB * P * P);
+  const ChebStep<T> none{};
   constexpr bool MCOK = P == 4 && sizeof(T) == 4;  // FP32 lines of p = 4 may use the matrix cores
   if (MCOK && M.lines_mfma) {
     if (kappa && partial)
-      hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+      hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, MCOK, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                         partial, none);
     else if (kappa)
-      hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+      hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, MCOK, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                         partial, none);
     else if (partial)
-      hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+      hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, MCOK, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                         partial, none);
     else
-      hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, MCOK>), grid, block, 0, s, x, y, kappa, ap, partial);
+      hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, MCOK, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                         partial, none);
     return hipGetLastError();
   }
   if (kappa && partial)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, true, false, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                       partial, none);
   else if (kappa)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, false, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                       partial, none);
   else if (partial)
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, true, false, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                       partial, none);
   else
-    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, false>), grid, block, 0, s, x, y, kappa, ap, partial);
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, false, EPI_STORE>), grid, block, 0, s, x, y, kappa, ap,
+                       partial, none);
   return hipGetLastError();
+}
+
+// One fused Chebyshev step (apply, residual, optional block-Jacobi inverse,
+// update): reads z, writes zout (and d unless last).
+template <int P, typename T>
+hipError_t launch_cheb_apply(const dg_mesh& M, const T* z, T* zout, const T* kappa, const ChebStep<T>& cs, bool bj,
+                             double* partial, hipStream_t s) {
+  constexpr int EB = CellsPerBlock<P>::value;
+  const int64_t G = grid_of(host_params<T>(M)[SP_APPLY]);
+  if (G > 0x7fffffff || M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const ScalarArgs<T>* ap = device_params<T>(M) + SP_APPLY;
+  const dim3 grid((unsigned)G), block(EB * P * P);
+  if (bj)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, false, EPI_CHEB_BJ>), grid, block, 0, s, z, zout, kappa,
+                       ap, partial, cs);
+  else if (kappa)
+    hipLaunchKernelGGL((k_scalar_apply<P, T, true, false, false, EPI_CHEB>), grid, block, 0, s, z, zout, kappa, ap,
+                       partial, cs);
+  else
+    hipLaunchKernelGGL((k_scalar_apply<P, T, false, false, false, EPI_CHEB>), grid, block, 0, s, z, zout, kappa, ap,
+                       partial, cs);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t dispatch_cheb_apply(const dg_mesh& M, const T* z, T* zout, const T* kappa, const ChebStep<T>& cs, bool bj,
+                               double* partial, hipStream_t s) {
+  switch (M.p) {
+    case 2: return launch_cheb_apply<2, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 3: return launch_cheb_apply<3, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 4: return launch_cheb_apply<4, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 5: return launch_cheb_apply<5, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 6: return launch_cheb_apply<6, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 7: return launch_cheb_apply<7, T>(M, z, zout, kappa, cs, bj, partial, s);
+    case 8: return launch_cheb_apply<8, T>(M, z, zout, kappa, cs, bj, partial, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int P, typename T>
@@ -1254,6 +1363,18 @@ hipError_t block_jacobi_update(const dg_mesh& M, int prec, void* r, const void* 
 }
 
 int64_t block_jacobi_blocks(const dg_mesh& M) { return grid_of(M.pd[SP_APPLY]); }
+
+hipError_t cheb_apply(const dg_mesh& M, int prec, const void* z, void* zout, const void* kappa, const void* r,
+                      const double* rd, void* d, double c1, double c2, bool last, bool bj, double* partial,
+                      hipStream_t s) {
+  if ((last && rd && !partial) || (bj && kappa)) return hipErrorInvalidValue;
+  if (prec == DG_F64) {
+    const ChebStep<double> cs{(const double*)r, rd, (double*)d, c1, c2, last ? 1 : 0};
+    return dispatch_cheb_apply<double>(M, (const double*)z, (double*)zout, (const double*)kappa, cs, bj, partial, s);
+  }
+  const ChebStep<float> cs{(const float*)r, rd, (float*)d, (float)c1, (float)c2, last ? 1 : 0};
+  return dispatch_cheb_apply<float>(M, (const float*)z, (float*)zout, (const float*)kappa, cs, bj, partial, s);
+}
 
 hipError_t cheb_block_jacobi(const dg_mesh& M, int prec, const void* r, const double* rd, const void* t, void* d,
                              void* z, double c1, double c2, bool first, bool last, double* partial, hipStream_t s) {

@@ -156,7 +156,7 @@ size_t layout(const dg_mesh& M, int mode, bool pc, bool kap, char* base, Work* w
   int64_t np = std::max(dgi::scalar_apply_blocks(M, DG_F64, kap), dgi::scalar_apply_blocks(M, DG_F32, kap));
   np = std::max<int64_t>(np, dgi::RED_BLOCKS);
   np = std::max<int64_t>(np, dgi::blas_cheb_blocks((int64_t)n));
-  if (pc) np = std::max(np, dgi::block_jacobi_blocks(M));
+  np = std::max(np, dgi::block_jacobi_blocks(M));
   w->partial = (double*)take(sizeof(double) * np);
   if (pc) w->partial2 = (double*)take(sizeof(double) * np);
   w->state = (dgi::CgState*)take(sizeof(dgi::CgState));
@@ -248,21 +248,32 @@ class Solver {
   // z = C r: s steps of the Chebyshev iteration for (P) A z = (P) r from z = 0
   // on [lo, hi], in precision `prec` (rin: the right-hand side in that
   // precision; rd: the same in FP64, from which the last step reads it and
-  // forms r.z), then r.z reduced into the state with `op`.
-  void cheb_precond(int prec, const void* rin, const double* rd, void* z, void* d, void* t, const void* kappa,
-                    int s, double lo, double hi, int op, int* applies) {
+  // forms r.z), then r.z reduced into the state with `op`. With `fused`, the
+  // steps k >= 1 run as one pass each (apply, residual, preconditioner and
+  // update together) that writes the new iterate to the other of z and t.
+  // Returns the vector that holds the result (z or t).
+  void* cheb_precond(int prec, const void* rin, const double* rd, void* z, void* d, void* t, const void* kappa,
+                     int s, double lo, double hi, int op, bool fused, int* applies) {
     const double theta = 0.5 * (hi + lo), delta = 0.5 * (hi - lo), sigma = theta / delta;
     double rho = 1.0 / sigma;
+    int64_t nb = pc_ ? dgi::block_jacobi_blocks(M_) : dgi::blas_cheb_blocks(n_);
     for (int k = 0; k < s; ++k) {
       const bool first = k == 0, last = k == s - 1;
       double c1 = 0.0, c2 = 1.0 / theta;
       if (!first) {
-        apply(prec, z, t, kappa);
-        ++*applies;
         const double rho_new = 1.0 / (2.0 * sigma - rho);
         c1 = rho_new * rho;
         c2 = 2.0 * rho_new / delta;
         rho = rho_new;
+        ++*applies;
+        if (fused) {
+          ck(dgi::cheb_apply(M_, prec, z, t, kappa, rin, last ? rd : nullptr, d, c1, c2, last, pc_, partial(), s_),
+             "Chebyshev step");
+          std::swap(z, t);
+          if (last) nb = dgi::block_jacobi_blocks(M_);
+          continue;
+        }
+        apply(prec, z, t, kappa);
       }
       if (pc_)
         ck(dgi::cheb_block_jacobi(M_, prec, rin, last ? rd : nullptr, t, d, z, c1, c2, first, last, partial(), s_),
@@ -271,8 +282,8 @@ class Solver {
         ck(dgi::blas_cheb_step(prec, rin, last ? rd : nullptr, t, d, z, c1, c2, first, last, n_, partial(), s_),
            "Chebyshev step");
     }
-    const int64_t nb = pc_ ? dgi::block_jacobi_blocks(M_) : dgi::blas_cheb_blocks(n_);
     ck(dgi::blas_finalize(partial(), nb, st(), op, s_), "r.z");
+    return z;
   }
 
   // nrm2 = |b - A x|^2 with r = b - A x (q is scratch)
@@ -378,6 +389,10 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       ck(dgi::blas_round_f32((const double*)kappa, w.k32, M->nqp, s), "kappa to FP32");
       kapc = w.k32;
     }
+    // the inner steps fused into the line kernel, unless the operator runs
+    // on the matrix-core kernel in this precision
+    const bool fused = !dgi::mfma_apply_supported(*M, ip, kapc != nullptr) &&
+                       !dgi::mfma_apply_f32_supported(*M, ip, kapc != nullptr);
     int total = 0, applies = 0, outer = 0;
     // 1. the first FP64 (P)CG iterations, recording their Lanczos coefficients
     ck(dgi::blas_state_from_norm(S.st(), s), "state");
@@ -406,10 +421,10 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
       const double hi = margin * lmax, lo = hi / ratio;
       ck(dgi::blas_state_from_norm(S.st(), s), "state");
       if (f32) ck(dgi::blas_round_f32(r, r32, n, s), "r to FP32");
-      S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi, dgi::OP_SET_RZ,
-                     &applies);
-      if (f32) ck(dgi::blas_widen(w.f[1], p, n, s), "p = z");
-      else ck(dgi::blas_copy(zv, p, DG_F64, n, s), "p = z");
+      void* zr = S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi,
+                                dgi::OP_SET_RZ, fused, &applies);
+      if (f32) ck(dgi::blas_widen((const float*)zr, p, n, s), "p = z");
+      else ck(dgi::blas_copy((const double*)zr, p, DG_F64, n, s), "p = z");
       const int cstep = std::max(1, check / deg);
       int it = 0, lost = 0;
       while (total < prm->maxit) {
@@ -430,11 +445,11 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
         if (f32) ck(dgi::blas_r_update_round(r, q, r32, n, S.partial(), S.st(), dgi::OP_RR, s), "residual update");
         else ck(dgi::blas_r_update(r, q, DG_F64, n, S.partial(), S.st(), dgi::OP_RR, s), "residual update");
         // z = C r with r.z; beta = r.z / previous r.z
-        S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi,
-                       dgi::OP_BETA_PC, &applies);
+        zr = S.cheb_precond(ip, f32 ? (const void*)r32 : (const void*)r, r, zc, dc, tc, kapc, deg, lo, hi,
+                            dgi::OP_BETA_PC, fused, &applies);
         // x += alpha p; p = z + beta p
-        if (f32) ck(dgi::blas_xp_update_mixed(x, p, w.f[1], n, S.st(), s), "x and p update");
-        else ck(dgi::blas_xp_update(x, p, zv, DG_F64, n, S.st(), s), "x and p update");
+        if (f32) ck(dgi::blas_xp_update_mixed(x, p, (const float*)zr, n, S.st(), s), "x and p update");
+        else ck(dgi::blas_xp_update(x, p, zr, DG_F64, n, S.st(), s), "x and p update");
         ++it;
         ++total;
       }
