@@ -183,6 +183,7 @@ struct dg_mesh {
   std::vector<double> vertices;   // host copy (perturbed meshes)
   double* d_vertices = nullptr;   // device copy
   double* d_gamma = nullptr;      // per-face penalties [3][faces of direction d]
+  double* d_cellgeo = nullptr;    // Stokes: coefficients of every cell's trilinear map
   // parameter blocks of the diffusion-reaction kernels (host copies and device copies)
   dgi::ScalarArgs<double> pd[dgi::SP_COUNT]{};
   dgi::ScalarArgs<float> pf[dgi::SP_COUNT]{};

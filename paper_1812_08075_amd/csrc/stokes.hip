@@ -9,25 +9,41 @@
 // pressure Q_{k-1} in the nodal basis at the k Gauss-Legendre points.
 //
 // Cells are images of the reference cube under the trilinear map of their
-// vertices, so J, det J and J^{-1} are evaluated at every quadrature point
-// from the 8 corners (Algorithm 1, part 2 with the geometry mu_T).
+// vertices, so the geometry is evaluated at every quadrature point
+// (Algorithm 1, part 2 with the geometry mu_T).
+//
+// Geometry. The trilinear map of a cell is written in monomial form,
+// x(xi) = a0 + a1 xi0 + a2 xi1 + a3 xi2 + a4 xi0 xi1 + a5 xi0 xi2 + a6 xi1 xi2
+// + a7 xi0 xi1 xi2, with a1..a7 per cell computed once at setup from the
+// corners; a column of J is then bilinear in the two other coordinates (three
+// multiply-adds per entry). J^{-1} is never formed: with rho_a the cross
+// product of the two other columns (rho_a = det J grad xi_a), the cell term
+// at a point is (w / |det J|) (rho_a . rho_b) d_b u_c - p w sgn(det J)
+// rho_a[c] and the divergence w sgn(det J) rho_a[c] d_a u_c. On a face of
+// normal direction d both cells share the tangential columns t1, t2 of J (the
+// face is the bilinear image of its four vertices), so n = t1 x t2, the area
+// element |n| w_a w_b and the outward unit normal are common to both sides,
+// and only the normal column differs; grad xi . nu follows from the Gram
+// entries of (t1, t2) and the dot products of the normal column with them.
 //
 // Work decomposition: one wave (64 threads) per cell.
-//  1. volume: thread = quadrature point. The nine reference derivatives
-//     d_a u_c are 1D contractions with D along a (Algorithm 1, part 1); the
-//     pressure at the point is the tensor interpolation A_p (x) A_p (x) A_p.
-//     The pointwise stage forms R_{c,a} = w |det J| (J^{-1} (J^{-T} g_c) -
-//     p J^{-1} e_c)_a and R_p = -w |det J| div u; the transposed
-//     contractions (part 3) give the cell residual of node i.
-//  2. faces (element-centric, all six at once): thread = face point. The own
-//     trace of u and of every reference derivative is the line's dot product
-//     with l_j(s) (normal direction first, Section 2.2). The neighbour's
-//     velocity trace and normal derivative come from its line in global
-//     memory; its tangential derivatives are D-contractions of its trace
-//     across the face points (through LDS). Flux at the face point, then the
-//     test functions of the own cell: value, normal derivative and the two
-//     tangential derivatives (D^T across face points), pressure by
-//     e_p (x) A_p^T (x) A_p^T.
+//  1. pressure: the cell's pressure at the points and the average of the two
+//     pressure traces at every face point, by sum factorization.
+//  2. volume: thread = quadrature point. The nine reference derivatives
+//     d_a u_c are 1D contractions with D along a (Algorithm 1, part 1), then
+//     the pointwise stage above; the transposed contractions (part 3) give
+//     the cell part of the velocity residual of node i, kept in registers.
+//  3. faces, in rounds of whole faces (64 points): thread = face point. The
+//     own trace of u and its normal derivative are the line's dot products
+//     with l_j(s), l'_j(s) (normal direction first, Section 2.2); the
+//     neighbour's come from its line in global memory; tangential
+//     derivatives are D-contractions across the face points (through LDS).
+//     The flux gives, per point, the coefficient of the test function's value
+//     and of its gradient along nu; the tangential parts of the latter are
+//     contracted across the face points (D^T) once per point, and every node
+//     then adds l_j(s) and l'_j(s) times its face's two coefficients.
+//  4. pressure test functions: the cell residual and the faces' [u].n terms
+//     through A_p^T (x) A_p^T (x) A_p^T and e_p (x) A_p^T (x) A_p^T.
 // Every output entry has one writer; no atomics; bitwise reproducible.
 #include <algorithm>
 #include <cmath>
@@ -41,120 +57,77 @@ namespace dgi {
 namespace {
 
 constexpr int NT = 64;
-
-// Trilinear map of the 8 corners X[c][a] (corner c = c0 + 2 c1 + 4 c2):
-// J[a][b] = d x_a / d xi_b at reference point xi.
-__device__ __forceinline__ void jacobian(const double* X, const double xi[3], double J[3][3]) {
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 3; ++b) J[a][b] = 0.0;
-#pragma unroll
-  for (int c = 0; c < 8; ++c) {
-    const int c0 = c & 1, c1 = (c >> 1) & 1, c2 = (c >> 2) & 1;
-    const double f0 = c0 ? xi[0] : 1.0 - xi[0];
-    const double f1 = c1 ? xi[1] : 1.0 - xi[1];
-    const double f2 = c2 ? xi[2] : 1.0 - xi[2];
-    const double d0 = (c0 ? 1.0 : -1.0) * f1 * f2;
-    const double d1 = f0 * (c1 ? 1.0 : -1.0) * f2;
-    const double d2 = f0 * f1 * (c2 ? 1.0 : -1.0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const double x = X[3 * c + a];
-      J[a][0] = fma(d0, x, J[a][0]);
-      J[a][1] = fma(d1, x, J[a][1]);
-      J[a][2] = fma(d2, x, J[a][2]);
-    }
-  }
-}
-
-// det J and J^{-1} (adjugate / det).
-__device__ __forceinline__ double invert(const double J[3][3], double Ji[3][3]) {
-  const double c00 = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  const double c01 = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  const double c02 = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  const double det = J[0][0] * c00 + J[0][1] * c01 + J[0][2] * c02;
-  const double id = 1.0 / det;
-  Ji[0][0] = c00 * id;
-  Ji[1][0] = c01 * id;
-  Ji[2][0] = c02 * id;
-  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) * id;
-  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) * id;
-  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) * id;
-  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) * id;
-  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) * id;
-  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) * id;
-  return det;
-}
+constexpr int GEO = 24;  // doubles per cell of the geometry table: a1..a7, 3 components each, padded
 
 struct StokesGeom {
-  const double* vertices;  // (nz+1)(ny+1)(nx+1) x 3
-  const double* gamma;     // per-face penalties, direction d at offset goff[d]
+  const double* cellgeo;  // GEO doubles per cell: a_m component k at 3 (m - 1) + k
+  const double* gamma;    // per-face penalties, direction d at offset goff[d]
   int64_t goff[3];
 };
 
-__device__ __forceinline__ void load_corners(const StokesGeom& g, const StokesArgs& a, int ex, int ey, int ez,
-                                             double* X, int t) {
-  if (t < 24) {
-    const int c = t / 3, k = t - 3 * c;
-    const int i = ex + (c & 1), j = ey + ((c >> 1) & 1), l = ez + ((c >> 2) & 1);
-    const int64_t v = i + (int64_t)(a.n[0] + 1) * (j + (int64_t)(a.n[1] + 1) * l);
-    X[t] = g.vertices[3 * v + k];
-  }
-}
-
-// Component c of the vector whose d-th entry is vd and whose two other entries,
-// in increasing index order, are va and vb (selects; no indexed register arrays).
-template <typename V>
-__device__ __forceinline__ V place(int d, int c, V vd, V va, V vb) {
-  if (c == 0) return d == 0 ? vd : va;
-  if (c == 1) return d == 0 ? va : (d == 1 ? vd : vb);
-  return d == 2 ? vd : vb;
-}
+// Offsets in a cell's geometry record: the xi_b coefficient and the xi_b xi_o one.
+__device__ __forceinline__ int g_lin(int b) { return 3 * b; }
+__device__ __forceinline__ int g_pair(int b, int o) { return 9 + 3 * (b + o - 1); }
+constexpr int G_TRI = 18;
 
 // Index of pressure node (jd along d, ja along t1, jb along t2) in the cell block.
 template <int KP>
 __device__ __forceinline__ int pnode(int d, int jd, int ja, int jb) {
-  return place(d, 0, jd, ja, jb) + KP * (place(d, 1, jd, ja, jb) + KP * place(d, 2, jd, ja, jb));
+  const int i0 = d == 0 ? jd : ja, i1 = d == 1 ? jd : (d == 0 ? ja : jb), i2 = d == 2 ? jd : jb;
+  return i0 + KP * (i1 + KP * i2);
 }
 
-__device__ __forceinline__ void face_dirs(int d, int& t1, int& t2) {
+__host__ __device__ __forceinline__ void face_dirs(int d, int& t1, int& t2) {
   t1 = d == 0 ? 1 : 0;
   t2 = d == 2 ? 1 : 2;
 }
 
+__device__ __forceinline__ void cross(const double* a, const double* b, double* c) {
+  c[0] = fma(a[1], b[2], -a[2] * b[1]);
+  c[1] = fma(a[2], b[0], -a[0] * b[2]);
+  c[2] = fma(a[0], b[1], -a[1] * b[0]);
+}
+
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+  return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
+}
+
+// Per face of the cell (FG doubles): tangential columns t1 = al1 + be xi_t2,
+// t2 = al2 + be xi_t1; the own normal column and the neighbour's, each
+// g0 + g1 xi_t1 + g2 xi_t2 + g3 xi_t1 xi_t2 (component k of coefficient m
+// at 3 m + k).
+constexpr int FG = 33;
+constexpr int FG_AL1 = 0, FG_AL2 = 3, FG_BE = 6, FG_OWN = 9, FG_NB = 21;
+
 template <int P>
-__global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ x, double* __restrict__ y,
-                                                     const StokesArgs a, const StokesGeom geo) {
+__device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double* __restrict__ y, const StokesArgs& a,
+                                            const StokesGeom& geo) {
   constexpr int KP = P - 1;
   constexpr int N = P * P * P, NQ = KP * KP * KP, L = P * P;
-  constexpr int NB = 3 * N + NQ;      // DOFs per cell
-  constexpr int NF = 6 * L;           // face points of the cell
-  constexpr int RA = (6 * NF > 10 * N) ? 6 * NF : 10 * N;
-  // staging of the pressure contractions: cell stages s1 [P KP^2], s2 [P^2 KP] and
-  // face-trace stages c1 [12 KP^2], c2 [12 P KP] live side by side; the test
-  // stages (KP P^2 + 6 KP P + KP^2 P + 6 KP^2) reuse the space later. Both
-  // run while the face coefficients are dead (before the faces' flux stage,
-  // after the velocity test functions), so the staging shares their space.
-  constexpr int TMP = P * KP * KP + P * P * KP + 12 * KP * KP + 12 * P * KP;
-  static_assert(KP * P * P + 6 * KP * P + KP * KP * P + 6 * KP * KP <= TMP, "pressure staging");
-  static_assert(TMP <= 9 * NF, "pressure staging inside the face coefficients");
+  constexpr int NB = 3 * N + NQ;                  // DOFs per cell
+  constexpr int NF = 6 * L;                       // face points of the cell
+  constexpr int FPR = NT / L;                     // whole faces per round
+  constexpr int NR = (6 + FPR - 1) / FPR;         // rounds
+  constexpr int RP = (FPR < 6 ? FPR : 6) * L;     // points of a full round
+  static_assert(N <= NT && FPR >= 1, "one volume point and at least one face per thread round");
+  // staging area X: pressure contractions (start), the cell residual sR[9][N]
+  // (volume), two quantities of 3 components per face point of a round
+  // (faces), pressure test contractions (end); the cell's pressure nodes and
+  // then its pressure residual at the points live at XR
+  constexpr int TMP0 = P * KP * KP + P * P * KP + 12 * KP * KP + 12 * P * KP;
+  constexpr int TMP1 = KP * P * P + 6 * KP * P + KP * KP * P + 6 * KP * KP;
+  constexpr int XR = (9 * N > 6 * RP) ? 9 * N : 6 * RP;
+  static_assert(TMP0 <= XR && TMP1 <= XR && NQ <= N, "staging");
+  __shared__ double tD[P * P], tE[2][P], tDE[2][P], tW[P], tX[P], tAp[P * KP], tEp[2][KP];
   __shared__ double su[3 * N];        // velocity
-  __shared__ double sp[NQ];           // pressure
-  __shared__ double sX[24];           // own corners
-  __shared__ double nX[6][24];        // neighbour corners
-  __shared__ double npr[6][NQ];       // neighbour pressure
-  __shared__ double spq[N];           // pressure at the quadrature points
-  __shared__ double fpT[NF], fpN[NF]; // pressure traces (own, neighbour) at the face points
-  __shared__ double regA[RA];         // faces: velocity traces fT[3][NF], fN[3][NF]; then cell residual sR[9][N], sRp[N]
-  __shared__ double fcoef[9 * NF];    // fV, fRg, fJn (below); pressure staging `tmp` at other times
-  __shared__ double fQ[NF];           // face coefficients of q
-  double* fV = fcoef;                 // face coefficients of v_c
-  double* fRg = fcoef + 3 * NF;       // face coefficients of grad v_c . nu
-  double* fJn = fcoef + 6 * NF;       // J^{-1} nu at the face points
-  double* tmp = fcoef;
-  double* fT = regA;
-  double* fN = regA + 3 * NF;
-  double* sR = regA;
-  double* sRp = regA + 9 * N;
+  __shared__ double fpA[NF];          // {p} at interior face points, p at boundary ones
+  __shared__ double fQ_spq[NF > N ? NF : N];  // pressure at the points (volume); face coefficients of q (faces)
+  __shared__ double fgeo[6 * FG];     // face geometry
+  __shared__ double X[XR + N];
+  double* spq = fQ_spq;
+  double* fQ = fQ_spq;
+  double* spl = X + XR;               // the cell's pressure nodes, then its pressure residual sRp
+  double* sRp = X + XR;
 
   const int t = threadIdx.x;
   const int e = blockIdx.x;
@@ -170,330 +143,408 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
     if (c >= 0 && c < a.n[d]) hasn |= 1u << f;
   }
   auto has_nb_of = [&](int f) { return ((hasn >> f) & 1u) != 0; };
-  // runtime-direction helpers (selects instead of indexed register arrays)
   auto ecd = [&](int d) { return d == 0 ? ec[0] : (d == 1 ? ec[1] : ec[2]); };
   auto estrd = [&](int d) { return d == 0 ? estr[0] : (d == 1 ? estr[1] : estr[2]); };
+  auto nb_of = [&](int f) { return (int64_t)e + ((f & 1) ? estrd(f >> 1) : -estrd(f >> 1)); };
+  const double* __restrict__ cg = geo.cellgeo + (int64_t)e * GEO;
 
   // ---- loads ---------------------------------------------------------------
+  if (t < P * P) tD[t] = a.D[t];
+  if (t < P) {
+    tE[0][t] = a.e[0][t];
+    tE[1][t] = a.e[1][t];
+    tDE[0][t] = a.de[0][t];
+    tDE[1][t] = a.de[1][t];
+    tW[t] = a.w[t];
+    tX[t] = a.xq[t];
+  }
+  if (t < P * KP) tAp[t] = a.Ap[t];
+  if (t < KP) {
+    tEp[0][t] = a.ep[0][t];
+    tEp[1][t] = a.ep[1][t];
+  }
   for (int i = t; i < 3 * N; i += NT) su[i] = x[base + i];
-  for (int i = t; i < NQ; i += NT) sp[i] = x[base + 3 * N + i];
-  load_corners(geo, a, ec[0], ec[1], ec[2], sX, t);
-#pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    if (!has_nb_of(f)) continue;
+  for (int i = t; i < NQ; i += NT) spl[i] = x[base + 3 * N + i];
+  if (t < 18) {  // face geometry: thread = (face, component)
+    const int f = t / 3, k = t - 3 * f;
     const int d = f >> 1, s = f & 1;
-    int nc[3] = {ec[0], ec[1], ec[2]};
-    nc[d] += s ? 1 : -1;
-    load_corners(geo, a, nc[0], nc[1], nc[2], nX[f], t);
-    const int64_t nb = (int64_t)e + (s ? estr[d] : -estr[d]);
-    for (int i = t; i < NQ; i += NT) npr[f][i] = x[nb * NB + 3 * N + i];
-  }
-  __syncthreads();
-
-  // ---- pressure by sum factorization: at the points, and face traces -------
-  // cell: (A_p x A_p x A_p) P, one direction per stage
-  double* s1 = tmp;              // [q0][j1][j2]
-  double* s2 = tmp + P * KP * KP; // [q0][q1][j2]
-  for (int i = t; i < P * KP * KP; i += NT) {
-    const int q0 = i % P, j12 = i / P;
-    double v = 0;
+    int t1, t2;
+    face_dirs(d, t1, t2);
+    const double sd = (double)s;
+    double* fg = fgeo + f * FG;
+    fg[FG_AL1 + k] = fma(sd, cg[g_pair(t1, d) + k], cg[g_lin(t1) + k]);
+    fg[FG_AL2 + k] = fma(sd, cg[g_pair(t2, d) + k], cg[g_lin(t2) + k]);
+    fg[FG_BE + k] = fma(sd, cg[G_TRI + k], cg[g_pair(t1, t2) + k]);
+    fg[FG_OWN + k] = cg[g_lin(d) + k];
+    fg[FG_OWN + 3 + k] = cg[g_pair(d, t1) + k];
+    fg[FG_OWN + 6 + k] = cg[g_pair(d, t2) + k];
+    fg[FG_OWN + 9 + k] = cg[G_TRI + k];
+    if (has_nb_of(f)) {
+      const double* __restrict__ gn = geo.cellgeo + nb_of(f) * GEO;
+      fg[FG_NB + k] = gn[g_lin(d) + k];
+      fg[FG_NB + 3 + k] = gn[g_pair(d, t1) + k];
+      fg[FG_NB + 6 + k] = gn[g_pair(d, t2) + k];
+      fg[FG_NB + 9 + k] = gn[G_TRI + k];
+    } else {
 #pragma unroll
-    for (int j0 = 0; j0 < KP; ++j0) v = fma(a.Ap[q0 * KP + j0], sp[j0 + KP * j12], v);
-    s1[i] = v;
-  }
-  // faces, stage 1: contract the normal direction with e_p(side) (own: side s, neighbour: 1 - s)
-  double* c1 = tmp + P * KP * KP + P * P * KP;  // [12][ja][jb]
-  for (int i = t; i < 12 * KP * KP; i += NT) {
-    const int fo = i / (KP * KP), r = i - fo * KP * KP;
-    const int f = fo >> 1, o = fo & 1;  // o: 0 own, 1 neighbour
-    const int d = f >> 1, s = f & 1;
-    const int ja = r % KP, jb = r / KP;
-    double v = 0;
-    if (o == 0 || has_nb_of(f)) {
-      const double* P_ = o ? npr[f] : sp;
-      const int side = o ? 1 - s : s;
-#pragma unroll
-      for (int jd = 0; jd < KP; ++jd) v = fma(a.ep[side][jd], P_[pnode<KP>(d, jd, ja, jb)], v);
+      for (int m = 0; m < 4; ++m) fg[FG_NB + 3 * m + k] = 0.0;
     }
-    c1[i] = v;
   }
   __syncthreads();
-  for (int i = t; i < P * P * KP; i += NT) {
-    const int q0 = i % P, q1 = (i / P) % P, j2 = i / (P * P);
-    double v = 0;
+
+  // ---- 1. pressure by sum factorization: at the points, and face traces -----
+  {
+    double* s1 = X;                       // [q0][j1][j2]
+    double* s2 = s1 + P * KP * KP;        // [q0][q1][j2]
+    double* c1 = s2 + P * P * KP;         // [12][ja][jb]: (face, own / neighbour)
+    double* c2 = c1 + 12 * KP * KP;       // [12][pa][jb]
+    for (int i = t; i < P * KP * KP; i += NT) {
+      const int q0 = i % P, j12 = i / P;
+      double v = 0;
 #pragma unroll
-    for (int j1 = 0; j1 < KP; ++j1) v = fma(a.Ap[q1 * KP + j1], s1[q0 + P * (j1 + KP * j2)], v);
-    s2[i] = v;
-  }
-  double* c2 = c1 + 12 * KP * KP;  // [12][pa][jb]
-  for (int i = t; i < 12 * P * KP; i += NT) {
-    const int fo = i / (P * KP), r = i - fo * P * KP;
-    const int pa = r % P, jb = r / P;
-    double v = 0;
+      for (int j0 = 0; j0 < KP; ++j0) v = fma(tAp[q0 * KP + j0], spl[j0 + KP * j12], v);
+      s1[i] = v;
+    }
+    // faces: contract the normal direction with e_p(side) (own: side s, neighbour: 1 - s)
+    for (int i = t; i < 12 * KP * KP; i += NT) {
+      const int fo = i / (KP * KP), r = i - fo * KP * KP;
+      const int f = fo >> 1, o = fo & 1;
+      const int d = f >> 1, s = f & 1;
+      const int ja = r % KP, jb = r / KP;
+      double v = 0;
+      if (o == 0) {
 #pragma unroll
-    for (int ja = 0; ja < KP; ++ja) v = fma(a.Ap[pa * KP + ja], c1[fo * KP * KP + ja + KP * jb], v);
-    c2[i] = v;
-  }
-  __syncthreads();
-  for (int i = t; i < N; i += NT) {
-    const int q01 = i % (P * P), q2 = i / (P * P);
-    double v = 0;
+        for (int jd = 0; jd < KP; ++jd) v = fma(tEp[s][jd], spl[pnode<KP>(d, jd, ja, jb)], v);
+      } else if (has_nb_of(f)) {
+        const double* __restrict__ pn = x + nb_of(f) * NB + 3 * N;
 #pragma unroll
-    for (int j2 = 0; j2 < KP; ++j2) v = fma(a.Ap[q2 * KP + j2], s2[q01 + P * P * j2], v);
-    spq[i] = v;
-  }
-  for (int i = t; i < 12 * L; i += NT) {
-    const int fo = i / L, pt = i - fo * L;
-    const int pa = pt % P, pb = pt / P;
-    double v = 0;
+        for (int jd = 0; jd < KP; ++jd) v = fma(tEp[1 - s][jd], pn[pnode<KP>(d, jd, ja, jb)], v);
+      }
+      c1[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < P * P * KP; i += NT) {
+      const int q0 = i % P, q1 = (i / P) % P, j2 = i / (P * P);
+      double v = 0;
 #pragma unroll
-    for (int jb = 0; jb < KP; ++jb) v = fma(a.Ap[pb * KP + jb], c2[fo * P * KP + pa + P * jb], v);
-    const int f = fo >> 1, o = fo & 1;
-    (o ? fpN : fpT)[f * L + pt] = v;
+      for (int j1 = 0; j1 < KP; ++j1) v = fma(tAp[q1 * KP + j1], s1[q0 + P * (j1 + KP * j2)], v);
+      s2[i] = v;
+    }
+    for (int i = t; i < 12 * P * KP; i += NT) {
+      const int fo = i / (P * KP), r = i - fo * P * KP;
+      const int pa = r % P, jb = r / P;
+      double v = 0;
+#pragma unroll
+      for (int ja = 0; ja < KP; ++ja) v = fma(tAp[pa * KP + ja], c1[fo * KP * KP + ja + KP * jb], v);
+      c2[i] = v;
+    }
+    __syncthreads();
+    for (int i = t; i < N; i += NT) {
+      const int q01 = i % (P * P), q2 = i / (P * P);
+      double v = 0;
+#pragma unroll
+      for (int j2 = 0; j2 < KP; ++j2) v = fma(tAp[q2 * KP + j2], s2[q01 + P * P * j2], v);
+      spq[i] = v;
+    }
+    for (int i = t; i < NF; i += NT) {
+      const int f = i / L, pt = i - f * L;
+      const int pa = pt % P, pb = pt / P;
+      double vo = 0, vn = 0;
+#pragma unroll
+      for (int jb = 0; jb < KP; ++jb) {
+        vo = fma(tAp[pb * KP + jb], c2[(2 * f) * P * KP + pa + P * jb], vo);
+        vn = fma(tAp[pb * KP + jb], c2[(2 * f + 1) * P * KP + pa + P * jb], vn);
+      }
+      fpA[i] = has_nb_of(f) ? 0.5 * (vo + vn) : vo;
+    }
+    __syncthreads();
   }
 
-  // ---- faces, phase 1: velocity traces and normal derivatives --------------
-  double dnT[2][3], dnN[2][3];
+  // ---- 2. cell terms at the points (Algorithm 1, parts 1 and 2) -------------
+  double* sR = X;
+  if (t < N) {
+    const int i = t;
+    const int i0 = i % P, i1 = (i / P) % P, i2 = i / L;
+    double g[3][3];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int fp = t + NT * r;
-    if (fp >= NF) continue;
-    const int f = fp / L, pt = fp - f * L;
-    const int d = f >> 1, s = f & 1;
-    const int pa = pt % P, pb = pt / P;
-    const int off = d == 0 ? P * pa + L * pb : (d == 1 ? pa + L * pb : pa + P * pb);
-    const int str = d == 0 ? 1 : (d == 1 ? P : L);
+    for (int c = 0; c < 3; ++c) g[c][0] = g[c][1] = g[c][2] = 0.0;
+#pragma unroll
+    for (int j = 0; j < P; ++j) {
+      const double d0 = tD[i0 * P + j], d1 = tD[i1 * P + j], d2 = tD[i2 * P + j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double* uc = su + c * N;
+        g[c][0] = fma(d0, uc[j + P * i1 + L * i2], g[c][0]);
+        g[c][1] = fma(d1, uc[i0 + P * j + L * i2], g[c][1]);
+        g[c][2] = fma(d2, uc[i0 + P * i1 + L * j], g[c][2]);
+      }
+    }
+    const double x0 = tX[i0], x1 = tX[i1], x2 = tX[i2];
+    const double x01 = x0 * x1, x02 = x0 * x2, x12 = x1 * x2;
+    double c0[3], c1[3], c2[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      c0[k] = fma(cg[G_TRI + k], x12, fma(cg[g_pair(0, 2) + k], x2, fma(cg[g_pair(0, 1) + k], x1, cg[g_lin(0) + k])));
+      c1[k] = fma(cg[G_TRI + k], x02, fma(cg[g_pair(1, 2) + k], x2, fma(cg[g_pair(0, 1) + k], x0, cg[g_lin(1) + k])));
+      c2[k] = fma(cg[G_TRI + k], x01, fma(cg[g_pair(1, 2) + k], x1, fma(cg[g_pair(0, 2) + k], x0, cg[g_lin(2) + k])));
+    }
+    double r0[3], r1[3], r2[3];
+    cross(c1, c2, r0);
+    cross(c2, c0, r1);
+    cross(c0, c1, r2);
+    const double det = dot3(c0, r0);
+    const double wq = tW[i0] * tW[i1] * tW[i2];
+    const double sc = wq / fabs(det);
+    const double wp = det < 0.0 ? -wq : wq;  // w sgn(det J)
+    const double G00 = sc * dot3(r0, r0), G11 = sc * dot3(r1, r1), G22 = sc * dot3(r2, r2);
+    const double G01 = sc * dot3(r0, r1), G02 = sc * dot3(r0, r2), G12 = sc * dot3(r1, r2);
+    const double pw = spq[i] * wp;
+    double div = 0.0;
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      double u = 0, dn = 0;
+      const double ga = g[c][0], gb = g[c][1], gc = g[c][2];
+      sR[(3 * c + 0) * N + i] = fma(G00, ga, fma(G01, gb, fma(G02, gc, -pw * r0[c])));
+      sR[(3 * c + 1) * N + i] = fma(G01, ga, fma(G11, gb, fma(G12, gc, -pw * r1[c])));
+      sR[(3 * c + 2) * N + i] = fma(G02, ga, fma(G12, gb, fma(G22, gc, -pw * r2[c])));
+      div = fma(r0[c], ga, fma(r1[c], gb, fma(r2[c], gc, div)));
+    }
+    sRp[i] = -wp * div;
+  }
+  __syncthreads();
+
+  // node of the thread for the test functions
+  const int n0 = t % P, n1 = (t / P) % P, n2 = t / L;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (t < N) {  // cell terms, part 3
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+      const double d0 = tD[q * P + n0], d1 = tD[q * P + n1], d2 = tD[q * P + n2];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        acc[c] = fma(d0, sR[(3 * c + 0) * N + q + P * n1 + L * n2], acc[c]);
+        acc[c] = fma(d1, sR[(3 * c + 1) * N + n0 + P * q + L * n2], acc[c]);
+        acc[c] = fma(d2, sR[(3 * c + 2) * N + n0 + P * n1 + L * q], acc[c]);
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- 3. faces, in rounds of whole faces ----------------------------------
+#pragma unroll
+  for (int rd = 0; rd < NR; ++rd) {
+    const int f = rd * FPR + t / L, pt = t % L;
+    const bool valid = t < FPR * L && f < 6;
+    const int d = f >> 1, s = f & 1;
+    const int pa = pt % P, pb = pt / P;
+    const int lb = (t / L) * L;  // first point of the thread's face in the round
+    double* sT = X;               // own velocity traces [3][RP]
+    double* sN = X + 3 * RP;      // neighbour's
+    double dnT[3] = {0.0, 0.0, 0.0}, dnN[3] = {0.0, 0.0, 0.0};
+    const bool has_nb = valid && has_nb_of(f);
+    if (valid) {
+      const int off = d == 0 ? P * pa + L * pb : (d == 1 ? pa + L * pb : pa + P * pb);
+      const int str = d == 0 ? 1 : (d == 1 ? P : L);
+      double es[P], ds[P];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const double v = su[c * N + off + j * str];
-        u = fma(a.e[s][j], v, u);
-        dn = fma(a.de[s][j], v, dn);
+        es[j] = tE[s][j];
+        ds[j] = tDE[s][j];
       }
-      fT[c * NF + fp] = u;
-      dnT[r][c] = dn;
-    }
-    if (has_nb_of(f)) {
-      const int64_t nb = (int64_t)e + (s ? estrd(d) : -estrd(d));
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double u = 0, dn = 0;
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          const double v = x[nb * NB + c * N + off + j * str];
-          u = fma(a.e[1 - s][j], v, u);
-          dn = fma(a.de[1 - s][j], v, dn);
+          const double v = su[c * N + off + j * str];
+          u = fma(es[j], v, u);
+          dn = fma(ds[j], v, dn);
         }
-        fN[c * NF + fp] = u;
-        dnN[r][c] = dn;
+        sT[c * RP + t] = u;
+        dnT[c] = dn;
       }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        fN[c * NF + fp] = 0.0;
-        dnN[r][c] = 0.0;
-      }
-    }
-  }
-  __syncthreads();
-
-  // ---- faces, phase 2: flux at every face point ---------------------------
-#pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    const int fp = t + NT * r;
-    if (fp >= NF) continue;
-    const int f = fp / L, pt = fp - f * L;
-    const int d = f >> 1, s = f & 1;
-    const int pa = pt % P, pb = pt / P;
-    const bool has_nb = has_nb_of(f);
-    const bool dir = (a.mask >> f) & 1u;
-    if (!has_nb && !dir) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        fV[c * NF + fp] = 0.0;
-        fRg[c * NF + fp] = 0.0;
-        fJn[c * NF + fp] = 0.0;
-      }
-      fQ[fp] = 0.0;
-      continue;
-    }
-    const int fb = f * L;
-    // geometry at the face point from the own cell
-    const double xs = (double)s, xa = a.xq[pa], xb = a.xq[pb];
-    const double xi[3] = {place(d, 0, xs, xa, xb), place(d, 1, xs, xa, xb), place(d, 2, xs, xa, xb)};
-    double J[3][3], Ji[3][3];
-    jacobian(sX, xi, J);
-    const double det = invert(J, Ji);
-    // row d of J^{-1} (the gradient of xi_d): normal direction
-    double rn[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) rn[k] = d == 0 ? Ji[0][k] : (d == 1 ? Ji[1][k] : Ji[2][k]);
-    const double nn = sqrt(rn[0] * rn[0] + rn[1] * rn[1] + rn[2] * rn[2]);
-    const double sg = s ? 1.0 : -1.0;
-    const double nu[3] = {sg * rn[0] / nn, sg * rn[1] / nn, sg * rn[2] / nn};
-    const double dA = fabs(det) * nn * a.w[pa] * a.w[pb];
-    const double Jn[3] = {Ji[0][0] * nu[0] + Ji[0][1] * nu[1] + Ji[0][2] * nu[2],
-                          Ji[1][0] * nu[0] + Ji[1][1] * nu[1] + Ji[1][2] * nu[2],
-                          Ji[2][0] * nu[0] + Ji[2][1] * nu[1] + Ji[2][2] * nu[2]};
-    // own full reference gradient along nu: normal part from phase 1, tangential
-    // parts by D across the face points of the own trace
-    double uT[3], gradT_n[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double ga = 0, gb = 0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        ga = fma(a.D[pa * P + j], fT[c * NF + fb + j + P * pb], ga);
-        gb = fma(a.D[pb * P + j], fT[c * NF + fb + pa + P * j], gb);
-      }
-      const double dn = dnT[r][c];
-      gradT_n[c] = Jn[0] * place(d, 0, dn, ga, gb) + Jn[1] * place(d, 1, dn, ga, gb) + Jn[2] * place(d, 2, dn, ga, gb);
-      uT[c] = fT[c * NF + fp];
-    }
-    const double pT = fpT[fp];
-    const int ct1 = d == 0 ? ec[1] : ec[0], ct2 = d == 2 ? ec[1] : ec[2];
-    const int nd = d == 0 ? a.n[0] : (d == 1 ? a.n[1] : a.n[2]);
-    const int nt1 = d == 0 ? a.n[1] : a.n[0];
-    const int64_t goff = d == 0 ? geo.goff[0] : (d == 1 ? geo.goff[1] : geo.goff[2]);
-    const double gam = geo.gamma[goff + (ecd(d) + s) + (int64_t)(nd + 1) * (ct1 + (int64_t)nt1 * ct2)];
-    double Rv[3], Rg[3], Rq = 0.0;
-    if (has_nb) {
-      const double xn[3] = {place(d, 0, 1.0 - xs, xa, xb), place(d, 1, 1.0 - xs, xa, xb),
-                            place(d, 2, 1.0 - xs, xa, xb)};
-      double JN[3][3], JiN[3][3];
-      jacobian(nX[f], xn, JN);
-      invert(JN, JiN);
-      const double JnN[3] = {JiN[0][0] * nu[0] + JiN[0][1] * nu[1] + JiN[0][2] * nu[2],
-                             JiN[1][0] * nu[0] + JiN[1][1] * nu[1] + JiN[1][2] * nu[2],
-                             JiN[2][0] * nu[0] + JiN[2][1] * nu[1] + JiN[2][2] * nu[2]};
-      const double pN = fpN[fp];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        double ga = 0, gb = 0;
+      if (has_nb) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          ga = fma(a.D[pa * P + j], fN[c * NF + fb + j + P * pb], ga);
-          gb = fma(a.D[pb * P + j], fN[c * NF + fb + pa + P * j], gb);
+          es[j] = tE[1 - s][j];
+          ds[j] = tDE[1 - s][j];
         }
-        const double dn = dnN[r][c];
-        const double gradN_n = JnN[0] * place(d, 0, dn, ga, gb) + JnN[1] * place(d, 1, dn, ga, gb) +
-                               JnN[2] * place(d, 2, dn, ga, gb);
-        const double jump = uT[c] - fN[c * NF + fp];
-        Rv[c] = dA * (-0.5 * (gradT_n[c] + gradN_n) + gam * jump + 0.5 * (pT + pN) * nu[c]);
-        Rg[c] = dA * 0.5 * a.theta * jump;
-        Rq += dA * 0.5 * jump * nu[c];
+        const double* __restrict__ xn = x + nb_of(f) * NB + off;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double u = 0, dn = 0;
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            const double v = xn[c * N + j * str];
+            u = fma(es[j], v, u);
+            dn = fma(ds[j], v, dn);
+          }
+          sN[c * RP + t] = u;
+          dnN[c] = dn;
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) sN[c * RP + t] = 0.0;
       }
-    } else {
+    }
+    __syncthreads();
+
+    // flux at the face point
+    double Rv[3] = {0.0, 0.0, 0.0}, G[3] = {0.0, 0.0, 0.0}, RJ1[3] = {0.0, 0.0, 0.0}, RJ2[3] = {0.0, 0.0, 0.0};
+    if (valid) {
+      const int fp = f * L + pt;
+      const bool dir = (a.mask >> f) & 1u;
+      double Rq = 0.0;
+      if (has_nb || dir) {
+        const double* fg = fgeo + f * FG;
+        const double xa = tX[pa], xb = tX[pb], xab = xa * xb;
+        double ct1[3], ct2[3], cd[3], cn[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          ct1[k] = fma(fg[FG_BE + k], xb, fg[FG_AL1 + k]);
+          ct2[k] = fma(fg[FG_BE + k], xa, fg[FG_AL2 + k]);
+          cd[k] = fma(fg[FG_OWN + 9 + k], xab,
+                      fma(fg[FG_OWN + 6 + k], xb, fma(fg[FG_OWN + 3 + k], xa, fg[FG_OWN + k])));
+        }
+        double n[3];
+        cross(ct1, ct2, n);
+        const double g11 = dot3(ct1, ct1), g22 = dot3(ct2, ct2), g12 = dot3(ct1, ct2);
+        const double nn2 = dot3(n, n), nn = sqrt(nn2);
+        const double detL = dot3(cd, n);
+        const double sg = (s ? 1.0 : -1.0) * (detL < 0.0 ? -1.0 : 1.0);
+        const double inn = 1.0 / nn;
+        const double nu[3] = {sg * inn * n[0], sg * inn * n[1], sg * inn * n[2]};
+        const double dA = nn * tW[pa] * tW[pb];
+        // grad xi_(d, t1, t2) . nu of the own cell
+        const double ka = sg * inn / detL;
+        const double q1 = dot3(cd, ct1), q2 = dot3(cd, ct2);
+        const double Jd = ka * nn2, J1 = ka * fma(g12, q2, -g22 * q1), J2 = ka * fma(g12, q1, -g11 * q2);
+        // own normal derivative: tangential parts by D across the face points
+        double gT[3], uT[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          double ga = 0, gb = 0;
+#pragma unroll
+          for (int j = 0; j < P; ++j) {
+            ga = fma(tD[pa * P + j], sT[c * RP + lb + j + P * pb], ga);
+            gb = fma(tD[pb * P + j], sT[c * RP + lb + pa + P * j], gb);
+          }
+          gT[c] = fma(Jd, dnT[c], fma(J1, ga, J2 * gb));
+          uT[c] = sT[c * RP + t];
+        }
+        const double pA = fpA[fp];
+        int t1, t2;
+        face_dirs(d, t1, t2);
+        const int ct1i = ecd(t1), ct2i = ecd(t2);
+        const int nd = a.n[d], nt1 = a.n[t1];
+        const int64_t goff = d == 0 ? geo.goff[0] : (d == 1 ? geo.goff[1] : geo.goff[2]);
+        const double gam = geo.gamma[goff + (ecd(d) + s) + (int64_t)(nd + 1) * (ct1i + (int64_t)nt1 * ct2i)];
+        double Rg[3];
+        if (has_nb) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            cn[k] = fma(fg[FG_NB + 9 + k], xab, fma(fg[FG_NB + 6 + k], xb, fma(fg[FG_NB + 3 + k], xa, fg[FG_NB + k])));
+          const double kb = sg * inn / dot3(cn, n);
+          const double p1 = dot3(cn, ct1), p2 = dot3(cn, ct2);
+          const double Nd = kb * nn2, N1 = kb * fma(g12, p2, -g22 * p1), N2 = kb * fma(g12, p1, -g11 * p2);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            double ga = 0, gb = 0;
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+              ga = fma(tD[pa * P + j], sN[c * RP + lb + j + P * pb], ga);
+              gb = fma(tD[pb * P + j], sN[c * RP + lb + pa + P * j], gb);
+            }
+            const double gN = fma(Nd, dnN[c], fma(N1, ga, N2 * gb));
+            const double jump = uT[c] - sN[c * RP + t];
+            Rv[c] = dA * (fma(-0.5, gT[c] + gN, gam * jump) + pA * nu[c]);
+            Rg[c] = dA * 0.5 * a.theta * jump;
+            Rq = fma(dA * 0.5 * jump, nu[c], Rq);
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            Rv[c] = dA * (fma(gam, uT[c], -gT[c]) + pA * nu[c]);
+            Rg[c] = dA * a.theta * uT[c];
+            Rq = fma(dA * uT[c], nu[c], Rq);
+          }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          G[c] = Rg[c] * Jd;
+          RJ1[c] = Rg[c] * J1;
+          RJ2[c] = Rg[c] * J2;
+        }
+      }
+      fQ[fp] = Rq;
+    }
+    __syncthreads();
+    double* sJ1 = X;            // Rg (grad xi_t1 . nu) [3][RP]
+    double* sJ2 = X + 3 * RP;   // Rg (grad xi_t2 . nu)
+    if (valid) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        Rv[c] = dA * (-gradT_n[c] + gam * uT[c] + pT * nu[c]);
-        Rg[c] = dA * a.theta * uT[c];
-        Rq += dA * uT[c] * nu[c];
+        sJ1[c * RP + t] = RJ1[c];
+        sJ2[c * RP + t] = RJ2[c];
       }
     }
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      fV[c * NF + fp] = Rv[c];
-      fRg[c * NF + fp] = Rg[c];
-      fJn[c * NF + fp] = Jn[c];
-    }
-    fQ[fp] = Rq;
-  }
-  __syncthreads();
-
-  // ---- cell terms at the points (Algorithm 1, parts 1 and 2) ---------------
-  for (int i = t; i < N; i += NT) {
-    const int i0 = i % P, i1 = (i / P) % P, i2 = i / L;
-    double g[3][3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      const double* uc = su + c * N;
-      double g0 = 0, g1 = 0, g2 = 0;
-#pragma unroll
-      for (int j = 0; j < P; ++j) {
-        g0 = fma(a.D[i0 * P + j], uc[j + P * i1 + L * i2], g0);
-        g1 = fma(a.D[i1 * P + j], uc[i0 + P * j + L * i2], g1);
-        g2 = fma(a.D[i2 * P + j], uc[i0 + P * i1 + L * j], g2);
-      }
-      g[c][0] = g0;
-      g[c][1] = g1;
-      g[c][2] = g2;
-    }
-    const double pq = spq[i];
-    const double xi[3] = {a.xq[i0], a.xq[i1], a.xq[i2]};
-    double J[3][3], Ji[3][3];
-    jacobian(sX, xi, J);
-    const double det = invert(J, Ji);
-    const double wd = a.w[i0] * a.w[i1] * a.w[i2] * fabs(det);
-    double div = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double gp[3];  // physical gradient J^{-T} g
-#pragma unroll
-      for (int jj = 0; jj < 3; ++jj) gp[jj] = Ji[0][jj] * g[c][0] + Ji[1][jj] * g[c][1] + Ji[2][jj] * g[c][2];
-      div += gp[c];
-#pragma unroll
-      for (int aa = 0; aa < 3; ++aa)
-        sR[(3 * c + aa) * N + i] =
-            wd * (Ji[aa][0] * gp[0] + Ji[aa][1] * gp[1] + Ji[aa][2] * gp[2] - pq * Ji[aa][c]);
-    }
-    sRp[i] = -wd * div;
-  }
-  __syncthreads();
-
-  // ---- test functions: cell terms (part 3) plus the six faces --------------
-  for (int i = t; i < N; i += NT) {
-    const int ii[3] = {i % P, (i / P) % P, i / L};
-    double acc[3];
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < P; ++q) {
-        s = fma(a.D[q * P + ii[0]], sR[(3 * c + 0) * N + q + P * ii[1] + L * ii[2]], s);
-        s = fma(a.D[q * P + ii[1]], sR[(3 * c + 1) * N + ii[0] + P * q + L * ii[2]], s);
-        s = fma(a.D[q * P + ii[2]], sR[(3 * c + 2) * N + ii[0] + P * ii[1] + L * q], s);
-      }
-      acc[c] = s;
-    }
-#pragma unroll
-    for (int f = 0; f < 6; ++f) {
-      const int d = f >> 1, s = f & 1;
-      int t1, t2;
-      face_dirs(d, t1, t2);
-      const int j = ii[d], pa = ii[t1], pb = ii[t2];
-      const int fb = f * L;
-      const double es = a.e[s][j], des = a.de[s][j];
-      const int fpt = fb + pa + P * pb;
+    __syncthreads();
+    // coefficient of the test function's value: Rv plus the tangential parts
+    // of the gradient term, contracted across the face points
+    if (valid) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        const double* Rg = fRg + c * NF;
-        double tv = fV[c * NF + fpt];
+        double v = Rv[c];
 #pragma unroll
         for (int q = 0; q < P; ++q) {
-          const int f1 = fb + q + P * pb, f2 = fb + pa + P * q;
-          tv = fma(a.D[q * P + pa], Rg[f1] * fJn[t1 * NF + f1], tv);
-          tv = fma(a.D[q * P + pb], Rg[f2] * fJn[t2 * NF + f2], tv);
+          v = fma(tD[q * P + pa], sJ1[c * RP + lb + q + P * pb], v);
+          v = fma(tD[q * P + pb], sJ2[c * RP + lb + pa + P * q], v);
         }
-        acc[c] = fma(es, tv, fma(des, Rg[fpt] * fJn[d * NF + fpt], acc[c]));
+        Rv[c] = v;
       }
     }
+    __syncthreads();
+    double* sV = X;            // value coefficient [3][RP]
+    double* sG = X + 3 * RP;   // normal-derivative coefficient
+    if (valid) {
 #pragma unroll
-    for (int c = 0; c < 3; ++c) y[base + c * N + i] = acc[c];
+      for (int c = 0; c < 3; ++c) {
+        sV[c * RP + t] = Rv[c];
+        sG[c * RP + t] = G[c];
+      }
+    }
+    __syncthreads();
+    if (t < N) {
+#pragma unroll
+      for (int lf = 0; lf < FPR; ++lf) {
+        const int ff = rd * FPR + lf;
+        if (ff >= 6) break;
+        const int fd = ff >> 1, fs = ff & 1;
+        const int j = fd == 0 ? n0 : (fd == 1 ? n1 : n2);
+        const int qa = fd == 0 ? n1 : n0, qb = fd == 2 ? n1 : n2;
+        const int idx = lf * L + qa + P * qb;
+        const double es = tE[fs][j], ds = tDE[fs][j];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) acc[c] = fma(es, sV[c * RP + idx], fma(ds, sG[c * RP + idx], acc[c]));
+      }
+    }
+    __syncthreads();
   }
-  // pressure test functions by sum factorization: cell (A_p^T x3) R_p and, per
-  // face, e_p(s) (x) (A_p^T x A_p^T) Q_f; the staging overwrites the face
-  // coefficients, read above by every thread
-  __syncthreads();
-  double* t1b = tmp;                      // [j0][q1][q2]
-  double* u1 = tmp + KP * P * P;          // [f][ja][pb]
+  if (t < N) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) y[base + c * N + t] = acc[c];
+  }
+
+  // ---- 4. pressure test functions by sum factorization: cell (A_p^T x3) R_p
+  // and, per face, e_p(s) (x) (A_p^T x A_p^T) Q_f
+  double* t1b = X;                        // [j0][q1][q2]
+  double* u1 = t1b + KP * P * P;          // [f][ja][pb]
+  double* t2b = u1 + 6 * KP * P;          // [j0][j1][q2]
+  double* u2 = t2b + KP * KP * P;         // [f][ja][jb]
   for (int i = t; i < KP * P * P; i += NT) {
     const int j0 = i % KP, q12 = i / KP;
     double v = 0;
 #pragma unroll
-    for (int q0 = 0; q0 < P; ++q0) v = fma(a.Ap[q0 * KP + j0], sRp[q0 + P * q12], v);
+    for (int q0 = 0; q0 < P; ++q0) v = fma(tAp[q0 * KP + j0], sRp[q0 + P * q12], v);
     t1b[i] = v;
   }
   for (int i = t; i < 6 * KP * P; i += NT) {
@@ -501,17 +552,15 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
     const int ja = r % KP, pb = r / KP;
     double v = 0;
 #pragma unroll
-    for (int pa = 0; pa < P; ++pa) v = fma(a.Ap[pa * KP + ja], fQ[f * L + pa + P * pb], v);
+    for (int pa = 0; pa < P; ++pa) v = fma(tAp[pa * KP + ja], fQ[f * L + pa + P * pb], v);
     u1[i] = v;
   }
   __syncthreads();
-  double* t2b = u1 + 6 * KP * P;          // [j0][j1][q2]
-  double* u2 = t2b + KP * KP * P;         // [f][ja][jb]
   for (int i = t; i < KP * KP * P; i += NT) {
     const int j0 = i % KP, j1 = (i / KP) % KP, q2 = i / (KP * KP);
     double v = 0;
 #pragma unroll
-    for (int q1 = 0; q1 < P; ++q1) v = fma(a.Ap[q1 * KP + j1], t1b[j0 + KP * (q1 + P * q2)], v);
+    for (int q1 = 0; q1 < P; ++q1) v = fma(tAp[q1 * KP + j1], t1b[j0 + KP * (q1 + P * q2)], v);
     t2b[i] = v;
   }
   for (int i = t; i < 6 * KP * KP; i += NT) {
@@ -519,7 +568,7 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
     const int ja = r % KP, jb = r / KP;
     double v = 0;
 #pragma unroll
-    for (int pb = 0; pb < P; ++pb) v = fma(a.Ap[pb * KP + jb], u1[f * KP * P + ja + KP * pb], v);
+    for (int pb = 0; pb < P; ++pb) v = fma(tAp[pb * KP + jb], u1[f * KP * P + ja + KP * pb], v);
     u2[i] = v;
   }
   __syncthreads();
@@ -527,16 +576,28 @@ __global__ void __launch_bounds__(NT) k_stokes_apply(const double* __restrict__ 
     const int jj[3] = {i % KP, (i / KP) % KP, i / (KP * KP)};
     double v = 0;
 #pragma unroll
-    for (int q2 = 0; q2 < P; ++q2) v = fma(a.Ap[q2 * KP + jj[2]], t2b[jj[0] + KP * (jj[1] + KP * q2)], v);
+    for (int q2 = 0; q2 < P; ++q2) v = fma(tAp[q2 * KP + jj[2]], t2b[jj[0] + KP * (jj[1] + KP * q2)], v);
 #pragma unroll
     for (int f = 0; f < 6; ++f) {
       const int d = f >> 1, s = f & 1;
       int t1, t2;
       face_dirs(d, t1, t2);
-      v = fma(a.ep[s][jj[d]], u2[f * KP * KP + jj[t1] + KP * jj[t2]], v);
+      v = fma(tEp[s][jj[d]], u2[f * KP * KP + jj[t1] + KP * jj[t2]], v);
     }
     y[base + 3 * N + i] = v;
   }
+}
+
+// k = 3: at most 128 VGPRs, so that four wavefronts fit per SIMD beside the
+// 10 KB of LDS per cell
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+    k_stokes_apply_q3(const double* __restrict__ x, double* __restrict__ y, const StokesArgs a, const StokesGeom geo) {
+  stokes_cell<4>(x, y, a, geo);
+}
+
+__global__ void __launch_bounds__(NT)
+    k_stokes_apply_q2(const double* __restrict__ x, double* __restrict__ y, const StokesArgs a, const StokesGeom geo) {
+  stokes_cell<3>(x, y, a, geo);
 }
 
 // Host-side trilinear geometry for the penalties.
@@ -675,27 +736,47 @@ void stokes_setup(dg_mesh& M) {
           gam[M.gamma_off[d] + pl + (int64_t)(n[d] + 1) * (c1 + (int64_t)n[t1] * c2)] = coef * area / vmin;
         }
   }
+  // monomial coefficients a1..a7 of every cell's trilinear map (corner c =
+  // c0 + 2 c1 + 4 c2; a_m is the alternating sum of the corners over the
+  // face, edge or cell spanned by the coordinates of the monomial)
+  std::vector<double> cgeo((size_t)M.nelem * GEO, 0.0);
+  for (int64_t e = 0; e < M.nelem; ++e) {
+    double X[8][3];
+    cell_corners(M, e, X);
+    double* g = &cgeo[(size_t)e * GEO];
+    for (int k = 0; k < 3; ++k) {
+      g[0 + k] = X[1][k] - X[0][k];
+      g[3 + k] = X[2][k] - X[0][k];
+      g[6 + k] = X[4][k] - X[0][k];
+      g[9 + k] = X[3][k] - X[2][k] - X[1][k] + X[0][k];
+      g[12 + k] = X[5][k] - X[4][k] - X[1][k] + X[0][k];
+      g[15 + k] = X[6][k] - X[4][k] - X[2][k] + X[0][k];
+      g[18 + k] = X[7][k] - X[6][k] - X[5][k] + X[4][k] - X[3][k] + X[2][k] + X[1][k] - X[0][k];
+    }
+  }
   if (hipMalloc(&M.d_vertices, sizeof(double) * M.vertices.size()) != hipSuccess ||
-      hipMalloc(&M.d_gamma, sizeof(double) * gam.size()) != hipSuccess) {
+      hipMalloc(&M.d_gamma, sizeof(double) * gam.size()) != hipSuccess ||
+      hipMalloc(&M.d_cellgeo, sizeof(double) * cgeo.size()) != hipSuccess) {
     (void)hipGetLastError();
     throw std::runtime_error("device allocation failed (Stokes geometry)");
   }
   if (hipMemcpy(M.d_vertices, M.vertices.data(), sizeof(double) * M.vertices.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
-      hipMemcpy(M.d_gamma, gam.data(), sizeof(double) * gam.size(), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(M.d_gamma, gam.data(), sizeof(double) * gam.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(M.d_cellgeo, cgeo.data(), sizeof(double) * cgeo.size(), hipMemcpyHostToDevice) != hipSuccess)
     throw std::runtime_error("upload of the Stokes geometry failed");
 }
 
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s) {
   StokesGeom g;
-  g.vertices = M.d_vertices;
+  g.cellgeo = M.d_cellgeo;
   g.gamma = M.d_gamma;
   for (int d = 0; d < 3; ++d) g.goff[d] = M.gamma_off[d];
   if (M.nelem > 0x7fffffff) return hipErrorInvalidValue;
   if (M.p == 4)
-    hipLaunchKernelGGL(k_stokes_apply<4>, dim3((unsigned)M.nelem), dim3(NT), 0, s, x, y, M.st, g);
+    hipLaunchKernelGGL(k_stokes_apply_q3, dim3((unsigned)M.nelem), dim3(NT), 0, s, x, y, M.st, g);
   else if (M.p == 3)
-    hipLaunchKernelGGL(k_stokes_apply<3>, dim3((unsigned)M.nelem), dim3(NT), 0, s, x, y, M.st, g);
+    hipLaunchKernelGGL(k_stokes_apply_q2, dim3((unsigned)M.nelem), dim3(NT), 0, s, x, y, M.st, g);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
