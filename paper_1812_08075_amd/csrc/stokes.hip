@@ -92,6 +92,20 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
   return fma(a[0], b[0], fma(a[1], b[1], a[2] * b[2]));
 }
 
+// 1/x and 1/sqrt(x): the hardware estimate refined by two Newton steps
+// (each squares the relative error) to the last bits of FP64.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = fma(0.5 * r, fma(-x * r, r, 1.0), r);
+  return fma(0.5 * r, fma(-x * r, r, 1.0), r);
+}
+
 // Per face of the cell (FG doubles): tangential columns t1 = al1 + be xi_t2,
 // t2 = al2 + be xi_t1; the own normal column and the neighbour's, each
 // g0 + g1 xi_t1 + g2 xi_t2 + g3 xi_t1 xi_t2 (component k of coefficient m
@@ -123,6 +137,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   __shared__ double fpA[NF];          // {p} at interior face points, p at boundary ones
   __shared__ double fQ_spq[NF > N ? NF : N];  // pressure at the points (volume); face coefficients of q (faces)
   __shared__ double fgeo[6 * FG];     // face geometry
+  __shared__ int sNb[6];              // the cell across face f, -1 on the boundary
   __shared__ double X[XR + N];
   double* spq = fQ_spq;
   double* fQ = fQ_spq;
@@ -145,50 +160,99 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   auto has_nb_of = [&](int f) { return ((hasn >> f) & 1u) != 0; };
   auto ecd = [&](int d) { return d == 0 ? ec[0] : (d == 1 ? ec[1] : ec[2]); };
   auto estrd = [&](int d) { return d == 0 ? estr[0] : (d == 1 ? estr[1] : estr[2]); };
-  auto nb_of = [&](int f) { return (int64_t)e + ((f & 1) ? estrd(f >> 1) : -estrd(f >> 1)); };
+  // the cell across face f (lane-varying f: a chain of selects of uniform values)
+  const int nxy = nx * ny;
+  auto nb_of = [&](int f) -> int64_t {
+    int v = e + nxy;
+    v = f == 4 ? e - nxy : v;
+    v = f == 3 ? e + nx : v;
+    v = f == 2 ? e - nx : v;
+    v = f == 1 ? e + 1 : v;
+    v = f == 0 ? e - 1 : v;
+    return v;
+  };
   const double* __restrict__ cg = geo.cellgeo + (int64_t)e * GEO;
 
-  // ---- loads ---------------------------------------------------------------
-  if (t < P * P) tD[t] = a.D[t];
-  if (t < P) {
-    tE[0][t] = a.e[0][t];
-    tE[1][t] = a.e[1][t];
-    tDE[0][t] = a.de[0][t];
-    tDE[1][t] = a.de[1][t];
-    tW[t] = a.w[t];
-    tX[t] = a.xq[t];
-  }
-  if (t < P * KP) tAp[t] = a.Ap[t];
-  if (t < KP) {
-    tEp[0][t] = a.ep[0][t];
-    tEp[1][t] = a.ep[1][t];
-  }
-  for (int i = t; i < 3 * N; i += NT) su[i] = x[base + i];
-  for (int i = t; i < NQ; i += NT) spl[i] = x[base + 3 * N + i];
-  if (t < 18) {  // face geometry: thread = (face, component)
-    const int f = t / 3, k = t - 3 * f;
-    const int d = f >> 1, s = f & 1;
-    int t1, t2;
-    face_dirs(d, t1, t2);
-    const double sd = (double)s;
-    double* fg = fgeo + f * FG;
-    fg[FG_AL1 + k] = fma(sd, cg[g_pair(t1, d) + k], cg[g_lin(t1) + k]);
-    fg[FG_AL2 + k] = fma(sd, cg[g_pair(t2, d) + k], cg[g_lin(t2) + k]);
-    fg[FG_BE + k] = fma(sd, cg[G_TRI + k], cg[g_pair(t1, t2) + k]);
-    fg[FG_OWN + k] = cg[g_lin(d) + k];
-    fg[FG_OWN + 3 + k] = cg[g_pair(d, t1) + k];
-    fg[FG_OWN + 6 + k] = cg[g_pair(d, t2) + k];
-    fg[FG_OWN + 9 + k] = cg[G_TRI + k];
-    if (has_nb_of(f)) {
-      const double* __restrict__ gn = geo.cellgeo + nb_of(f) * GEO;
-      fg[FG_NB + k] = gn[g_lin(d) + k];
-      fg[FG_NB + 3 + k] = gn[g_pair(d, t1) + k];
-      fg[FG_NB + 6 + k] = gn[g_pair(d, t2) + k];
-      fg[FG_NB + 9 + k] = gn[G_TRI + k];
-    } else {
+  // ---- loads: every global load of the set-up is issued before the first
+  // LDS write, so that their latencies overlap
+  constexpr int NRU = (3 * N + NT - 1) / NT;
+  double vu[NRU];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) fg[FG_NB + 3 * m + k] = 0.0;
+  for (int r = 0; r < NRU; ++r) {
+    const int i = t + r * NT;
+    vu[r] = i < 3 * N ? x[base + i] : 0.0;
+  }
+  const double vp = t < NQ ? x[base + 3 * N + t] : 0.0;
+  const int tp = t < P ? t : 0, tq = t < KP ? t : 0;
+  const double vD = a.D[t < P * P ? t : 0], vAp = a.Ap[t < P * KP ? t : 0];
+  const double ve0 = a.e[0][tp], ve1 = a.e[1][tp], vd0 = a.de[0][tp], vd1 = a.de[1][tp];
+  const double vw = a.w[tp], vx = a.xq[tp], vq0 = a.ep[0][tq], vq1 = a.ep[1][tq];
+  // face geometry: thread = (face, component) for t < 18
+  const int gf = t < 18 ? t / 3 : 0, gk = t - 3 * gf;
+  const int gd = gf >> 1, gs = gf & 1;
+  int g1, g2;
+  face_dirs(gd, g1, g2);
+  double go[7], gq[4] = {0.0, 0.0, 0.0, 0.0};
+  if (t < 18) {
+    go[0] = cg[g_lin(g1) + gk];
+    go[1] = cg[g_pair(g1, gd) + gk];
+    go[2] = cg[g_lin(g2) + gk];
+    go[3] = cg[g_pair(g2, gd) + gk];
+    go[4] = cg[g_pair(g1, g2) + gk];
+    go[5] = cg[g_lin(gd) + gk];
+    go[6] = cg[G_TRI + gk];
+    if (has_nb_of(gf)) {
+      const double* __restrict__ gn = geo.cellgeo + nb_of(gf) * GEO;
+      gq[0] = gn[g_lin(gd) + gk];
+      gq[1] = gn[g_pair(gd, g1) + gk];
+      gq[2] = gn[g_pair(gd, g2) + gk];
+      gq[3] = gn[G_TRI + gk];
     }
+  }
+  // the neighbours' pressure nodes on the shared faces: thread = (face, ja, jb)
+  // for t < 6 KP^2, the KP nodes along the face normal
+  const int pf = t < 6 * KP * KP ? t / (KP * KP) : 0, pr = t - pf * KP * KP;
+  double vnp[KP];
+#pragma unroll
+  for (int jd = 0; jd < KP; ++jd) vnp[jd] = 0.0;
+  if (t < 6 * KP * KP && has_nb_of(pf)) {
+    const double* __restrict__ pn = x + nb_of(pf) * NB + 3 * N;
+#pragma unroll
+    for (int jd = 0; jd < KP; ++jd) vnp[jd] = pn[pnode<KP>(pf >> 1, jd, pr % KP, pr / KP)];
+  }
+  if (t < 6) sNb[t] = has_nb_of(t) ? (int)nb_of(t) : -1;
+#pragma unroll
+  for (int r = 0; r < NRU; ++r) {
+    const int i = t + r * NT;
+    if (i < 3 * N) su[i] = vu[r];
+  }
+  if (t < NQ) spl[t] = vp;
+  if (t < P * P) tD[t] = vD;
+  if (t < P * KP) tAp[t] = vAp;
+  if (t < P) {
+    tE[0][t] = ve0;
+    tE[1][t] = ve1;
+    tDE[0][t] = vd0;
+    tDE[1][t] = vd1;
+    tW[t] = vw;
+    tX[t] = vx;
+  }
+  if (t < KP) {
+    tEp[0][t] = vq0;
+    tEp[1][t] = vq1;
+  }
+  if (t < 18) {
+    const double sd = (double)gs;
+    double* fg = fgeo + gf * FG;
+    fg[FG_AL1 + gk] = fma(sd, go[1], go[0]);
+    fg[FG_AL2 + gk] = fma(sd, go[3], go[2]);
+    fg[FG_BE + gk] = fma(sd, go[6], go[4]);
+    fg[FG_OWN + gk] = go[5];
+    fg[FG_OWN + 3 + gk] = go[1];  // the xi_d xi_t1 and xi_d xi_t2 coefficients
+    fg[FG_OWN + 6 + gk] = go[3];
+    fg[FG_OWN + 9 + gk] = go[6];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) fg[FG_NB + 3 * m + gk] = gq[m];
   }
   __syncthreads();
 
@@ -206,21 +270,16 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
       s1[i] = v;
     }
     // faces: contract the normal direction with e_p(side) (own: side s, neighbour: 1 - s)
-    for (int i = t; i < 12 * KP * KP; i += NT) {
-      const int fo = i / (KP * KP), r = i - fo * KP * KP;
-      const int f = fo >> 1, o = fo & 1;
-      const int d = f >> 1, s = f & 1;
-      const int ja = r % KP, jb = r / KP;
-      double v = 0;
-      if (o == 0) {
+    if (t < 6 * KP * KP) {
+      const int d = pf >> 1, s = pf & 1;
+      double v = 0, vn = 0;
 #pragma unroll
-        for (int jd = 0; jd < KP; ++jd) v = fma(tEp[s][jd], spl[pnode<KP>(d, jd, ja, jb)], v);
-      } else if (has_nb_of(f)) {
-        const double* __restrict__ pn = x + nb_of(f) * NB + 3 * N;
-#pragma unroll
-        for (int jd = 0; jd < KP; ++jd) v = fma(tEp[1 - s][jd], pn[pnode<KP>(d, jd, ja, jb)], v);
+      for (int jd = 0; jd < KP; ++jd) {
+        v = fma(tEp[s][jd], spl[pnode<KP>(d, jd, pr % KP, pr / KP)], v);
+        vn = fma(tEp[1 - s][jd], vnp[jd], vn);
       }
-      c1[i] = v;
+      c1[(2 * pf) * KP * KP + pr] = v;
+      c1[(2 * pf + 1) * KP * KP + pr] = vn;
     }
     __syncthreads();
     for (int i = t; i < P * P * KP; i += NT) {
@@ -294,7 +353,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
     cross(c0, c1, r2);
     const double det = dot3(c0, r0);
     const double wq = tW[i0] * tW[i1] * tW[i2];
-    const double sc = wq / fabs(det);
+    const double sc = wq * recip(fabs(det));
     const double wp = det < 0.0 ? -wq : wq;  // w sgn(det J)
     const double G00 = sc * dot3(r0, r0), G11 = sc * dot3(r1, r1), G22 = sc * dot3(r2, r2);
     const double G01 = sc * dot3(r0, r1), G02 = sc * dot3(r0, r2), G12 = sc * dot3(r1, r2);
@@ -368,7 +427,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
           es[j] = tE[1 - s][j];
           ds[j] = tDE[1 - s][j];
         }
-        const double* __restrict__ xn = x + nb_of(f) * NB + off;
+        const double* __restrict__ xn = x + (int64_t)sNb[f] * NB + off;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           double u = 0, dn = 0;
@@ -408,14 +467,23 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
         double n[3];
         cross(ct1, ct2, n);
         const double g11 = dot3(ct1, ct1), g22 = dot3(ct2, ct2), g12 = dot3(ct1, ct2);
-        const double nn2 = dot3(n, n), nn = sqrt(nn2);
+        const double nn2 = dot3(n, n);
         const double detL = dot3(cd, n);
+        // the neighbour's normal column (its tangential ones are the own)
+        double detN = 1.0;
+        if (has_nb) {
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            cn[k] = fma(fg[FG_NB + 9 + k], xab, fma(fg[FG_NB + 6 + k], xb, fma(fg[FG_NB + 3 + k], xa, fg[FG_NB + k])));
+          detN = dot3(cn, n);
+        }
         const double sg = (s ? 1.0 : -1.0) * (detL < 0.0 ? -1.0 : 1.0);
-        const double inn = 1.0 / nn;
-        const double nu[3] = {sg * inn * n[0], sg * inn * n[1], sg * inn * n[2]};
-        const double dA = nn * tW[pa] * tW[pb];
+        const double rs = rsqrt_nr(nn2), srs = sg * rs;  // 1 / |n|, with the orientation
+        const double z = recip(detL * detN);
+        const double nu[3] = {srs * n[0], srs * n[1], srs * n[2]};
+        const double dA = nn2 * rs * tW[pa] * tW[pb];
         // grad xi_(d, t1, t2) . nu of the own cell
-        const double ka = sg * inn / detL;
+        const double ka = srs * detN * z;
         const double q1 = dot3(cd, ct1), q2 = dot3(cd, ct2);
         const double Jd = ka * nn2, J1 = ka * fma(g12, q2, -g22 * q1), J2 = ka * fma(g12, q1, -g11 * q2);
         // own normal derivative: tangential parts by D across the face points
@@ -440,10 +508,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
         const double gam = geo.gamma[goff + (ecd(d) + s) + (int64_t)(nd + 1) * (ct1i + (int64_t)nt1 * ct2i)];
         double Rg[3];
         if (has_nb) {
-#pragma unroll
-          for (int k = 0; k < 3; ++k)
-            cn[k] = fma(fg[FG_NB + 9 + k], xab, fma(fg[FG_NB + 6 + k], xb, fma(fg[FG_NB + 3 + k], xa, fg[FG_NB + k])));
-          const double kb = sg * inn / dot3(cn, n);
+          const double kb = srs * detL * z;
           const double p1 = dot3(cn, ct1), p2 = dot3(cn, ct2);
           const double Nd = kb * nn2, N1 = kb * fma(g12, p2, -g22 * p1), N2 = kb * fma(g12, p1, -g11 * p2);
 #pragma unroll
