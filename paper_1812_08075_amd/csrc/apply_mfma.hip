@@ -1,5 +1,6 @@
 // Matrix-core apply of the SIPG diffusion-reaction operator for k = 3 (p = 4
-// nodes per direction), FP64, kappa = 1, axis-aligned cells (gfx950).
+// nodes per direction), kappa = 1, axis-aligned cells (gfx950), on FP64 or
+// FP32 vectors.
 //
 // Operator (Section 5.2, eq. diffreac_weak, linear part) evaluated with the
 // sum-factorized structure of Algorithm 1 and the face treatment of Section
@@ -56,6 +57,20 @@
 //    then x, so that the z-neighbour cells are still in the XCD's L2. The
 //    hardware dispatches block b to XCD b mod 8; a table built on the host
 //    maps blocks to wavefront positions accordingly.
+//
+// FP32 vectors. The arithmetic is FP64 on the same operator tables and in
+// the same order, so the result is the FP64 kernel's result for the FP32
+// input, rounded once to FP32. A 16-byte load carries four FP32 values: a
+// whole x-line of a cell. The "quad layout" holds in one lane the four nodes
+// i0 = 0..3 of one x-line: lane = i1 + 4 c + 16 i2 for the z direction, lane
+// = i2 + 4 c + 16 i1 for the y direction, c the cell of the chunk; converted
+// to FP64, each of the four components is an operand of the same product.
+// Per step one 16-byte load each for row y + 1 and the two z-neighbour rows.
+//
+// The wavefront's march (the x direction, the LDS buffers, the order of the
+// directions, the reduction) is one template; the layout of the y and z
+// directions and of the loads and stores is a policy per precision
+// (PairLanes, QuadLanes).
 #include <algorithm>
 #include <vector>
 
@@ -88,6 +103,55 @@ __device__ __forceinline__ int side_type(bool has, bool dirichlet) {
   return has ? T_INT : (dirichlet ? T_DIR : T_NONE);
 }
 
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+
+struct Quad {
+  double v[4];
+};
+
+// 16-byte load of one FP32 x-line (zeros when !ok), widened to FP64
+__device__ __forceinline__ Quad load_quad(const float* p, bool ok) {
+  fvec4 r = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (ok) r = *reinterpret_cast<const fvec4*>(p);
+  Quad q;
+  q.v[0] = (double)r.x;
+  q.v[1] = (double)r.y;
+  q.v[2] = (double)r.z;
+  q.v[3] = (double)r.w;
+  return q;
+}
+
+__device__ __forceinline__ Quad lds_quad(const double* p) {
+  const dvec2 a = *reinterpret_cast<const dvec2*>(p);
+  const dvec2 b = *reinterpret_cast<const dvec2*>(p + 2);
+  Quad q;
+  q.v[0] = a.x;
+  q.v[1] = a.y;
+  q.v[2] = b.x;
+  q.v[3] = b.y;
+  return q;
+}
+
+__device__ __forceinline__ void lds_store_quad(double* p, const Quad& q) {
+  const dvec2 a = {q.v[0], q.v[1]};
+  const dvec2 b = {q.v[2], q.v[3]};
+  *reinterpret_cast<dvec2*>(p) = a;
+  *reinterpret_cast<dvec2*>(p + 2) = b;
+}
+
+// one direction on a quad register: K u + L u_left + R u_right per component
+__device__ __forceinline__ Quad quad_line(double K, double L, double R, const Quad& u, const Quad& ul,
+                                          const Quad& ur, bool h0, bool h1) {
+  Quad c;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    c.v[q] = mfma(K, u.v[q], 0.0);
+    if (h0) c.v[q] = mfma(L, ul.v[q], c.v[q]);
+    if (h1) c.v[q] = mfma(R, ur.v[q], c.v[q]);
+  }
+  return c;
+}
+
 // one direction on a pair register: K u + L u_left + R u_right per component
 __device__ __forceinline__ double2 pair_line(double K, double L, double R, double2 u, double2 ul, double2 ur,
                                              bool h0, bool h1) {
@@ -105,14 +169,179 @@ __device__ __forceinline__ double2 pair_line(double K, double L, double R, doubl
   return c;
 }
 
+// Operator entries of the lane (entry (lane % 4, lane / 16) of the x, y and
+// z line operators of an interior cell: K, L, R each).
+struct LineOps {
+  double Kx, Lx, Rx, Ky, Ly, Ry, Kz, Lz, Rz;
+};
+
+// FP64 vectors, pair layout: lane = h + 2 t + 8 c + 16 n, the register's
+// components the nodes i0 = 2h, 2h + 1 of cell c of a pair, (t, n) = (i1, i2)
+// in the z layout and (i2, i1) in the y layout.
+struct PairLanes {
+  using T = double;
+  struct Rows {
+    double2 v[2];
+  };
+  int pc, offz, lz, ly;
+  double2 wn;
+  __device__ __forceinline__ PairLanes(int lane, const ScalarArgs<double>& a, int, LineOps& op) {
+    const int h = lane & 1, t = (lane >> 1) & 3, n = lane >> 4;
+    pc = (lane >> 3) & 1;
+    offz = 2 * h + 4 * t + 16 * n + 64 * pc;
+    lz = 2 * h + LIS * t + LPS * n + LCS * pc;
+    ly = 2 * h + LPS * t + LIS * n + LCS * pc;
+    double2 rec[6];
+    const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) rec[k] = lr[k];
+    op = LineOps{rec[0].x, rec[0].y, rec[1].x, rec[1].y, rec[2].x, rec[2].y, rec[3].x, rec[3].y, rec[4].x};
+    wn = rec[5];
+  }
+  // rows y (buffer cur) and y - 1 (buffer oth) of the chunk at xc
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const double* xc, size_t sy, int nvalid,
+                                             bool has_prev) const {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const bool v = 2 * p + pc < nvalid;
+      const double2 u0 = load2(xc + 128 * p + offz, v);
+      const double2 um = load2(xc - sy + 128 * p + offz, v && has_prev);
+      *reinterpret_cast<double2*>(cur + 2 * LCS * p + lz) = u0;
+      *reinterpret_cast<double2*>(oth + 2 * LCS * p + lz) = um;
+    }
+  }
+  __device__ __forceinline__ Rows load_rows(const double* xc, int64_t off, int nvalid, bool ok) const {
+    Rows r;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) r.v[p] = load2(xc + off + 128 * p + offz, ok && 2 * p + pc < nvalid);
+    return r;
+  }
+  __device__ __forceinline__ Rows lds_y(const double* b) const {
+    Rows r;
+#pragma unroll
+    for (int p = 0; p < 2; ++p) r.v[p] = *reinterpret_cast<const double2*>(b + 2 * LCS * p + ly);
+    return r;
+  }
+  __device__ __forceinline__ void store_z(double* b, const Rows& r) const {
+#pragma unroll
+    for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(b + 2 * LCS * p + lz) = r.v[p];
+  }
+  // sr += the y lines of row cur (neighbours yl and the row in oth)
+  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yl, double Ky,
+                                          double Ly, double Ry, bool hy0, bool hy1, int nvalid) const {
+    double2 uy[2], yr[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      uy[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + ly);
+      yr[p] = *reinterpret_cast<const double2*>(oth + 2 * LCS * p + ly);
+    }
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (2 * p < nvalid) {
+        const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl.v[p], yr[p], hy0, hy1);
+        double2* r = reinterpret_cast<double2*>(sr + 2 * LCS * p + ly);
+        const double2 o = *r;
+        *r = make_double2(o.x + c.x, o.y + c.y);
+      }
+    }
+  }
+  // the z lines, the sum of the three directions times the tensor weight, the store
+  template <bool DOT>
+  __device__ __forceinline__ void z_stage(const double* cur, const double* sr, const Rows& zl, const Rows& zr,
+                                          double Kz, double Lz, double Rz, bool hz0, bool hz1, int nvalid,
+                                          double* __restrict__ yc, double& pq) const {
+    double2 uz[2];
+#pragma unroll
+    for (int p = 0; p < 2; ++p) uz[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + lz);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      if (2 * p < nvalid) {
+        const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl.v[p], zr.v[p], hz0, hz1);
+        const double2 o = *reinterpret_cast<const double2*>(sr + 2 * LCS * p + lz);
+        if (2 * p + pc < nvalid) {
+          const dvec2 v = {wn.x * (o.x + c.x), wn.y * (o.y + c.y)};
+          __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(yc + 128 * p + offz));
+          if (DOT) pq = fma(uz[p].y, v.y, fma(uz[p].x, v.x, pq));
+        }
+      }
+    }
+  }
+};
+
+// FP32 vectors, quad layout: one x-line of cell c per lane, lane = i1 + 4 c
+// + 16 i2 (z layout) or i2 + 4 c + 16 i1 (y layout).
+struct QuadLanes {
+  using T = float;
+  using Rows = Quad;
+  int offz, lz, ly;
+  bool cok;  // the lane's cell is in the chunk
+  double wq[4];
+  __device__ __forceinline__ QuadLanes(int lane, const ScalarArgs<double>& a, int nvalid, LineOps& op) {
+    const int c = (lane >> 2) & 3;
+    cok = c < nvalid;
+    const int zi1 = lane & 3, zi2 = lane >> 4;  // z layout
+    const int yi2 = lane & 3, yi1 = lane >> 4;  // y layout
+    offz = 64 * c + 4 * zi1 + 16 * zi2;
+    lz = LCS * c + LIS * zi1 + LPS * zi2;
+    ly = LCS * c + LIS * yi1 + LPS * yi2;
+    const double* rl = a.lrec[lane];
+    op = LineOps{rl[0], rl[1], rl[2], rl[3], rl[4], rl[5], rl[6], rl[7], rl[8]};
+    // the tensor weights of the lane's four nodes, from the records of the
+    // lanes that hold them in the pair layout
+#pragma unroll
+    for (int q = 0; q < 4; ++q) wq[q] = a.lrec[(q >> 1) + 2 * zi1 + 16 * zi2][10 + (q & 1)];
+  }
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const float* xc, size_t sy, int,
+                                             bool has_prev) const {
+    lds_store_quad(cur + lz, load_quad(xc + offz, cok));
+    lds_store_quad(oth + lz, load_quad(xc - sy + offz, cok && has_prev));
+  }
+  __device__ __forceinline__ Rows load_rows(const float* xc, int64_t off, int, bool ok) const {
+    return load_quad(xc + off + offz, cok && ok);
+  }
+  __device__ __forceinline__ Rows lds_y(const double* b) const { return lds_quad(b + ly); }
+  __device__ __forceinline__ void store_z(double* b, const Rows& r) const { lds_store_quad(b + lz, r); }
+  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yl, double Ky,
+                                          double Ly, double Ry, bool hy0, bool hy1, int) const {
+    const Quad cy = quad_line(Ky, Ly, Ry, lds_quad(cur + ly), yl, lds_quad(oth + ly), hy0, hy1);
+    Quad o = lds_quad(sr + ly);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) o.v[q] = o.v[q] + cy.v[q];
+    lds_store_quad(sr + ly, o);
+  }
+  template <bool DOT>
+  __device__ __forceinline__ void z_stage(const double* cur, const double* sr, const Rows& zl, const Rows& zr,
+                                          double Kz, double Lz, double Rz, bool hz0, bool hz1, int,
+                                          float* __restrict__ yc, double& pq) const {
+    const Quad uz = lds_quad(cur + lz);
+    const Quad cz = quad_line(Kz, Lz, Rz, uz, zl, zr, hz0, hz1);
+    const Quad o = lds_quad(sr + lz);
+    fvec4 v;
+    v.x = (float)(wq[0] * (o.v[0] + cz.v[0]));
+    v.y = (float)(wq[1] * (o.v[1] + cz.v[1]));
+    v.z = (float)(wq[2] * (o.v[2] + cz.v[2]));
+    v.w = (float)(wq[3] * (o.v[3] + cz.v[3]));
+    if (cok) {
+      __builtin_nontemporal_store(v, reinterpret_cast<fvec4*>(yc + offz));
+      if (DOT) {
+        pq = fma(uz.v[0], (double)v.x, pq);
+        pq = fma(uz.v[1], (double)v.y, pq);
+        pq = fma(uz.v[2], (double)v.z, pq);
+        pq = fma(uz.v[3], (double)v.w, pq);
+      }
+    }
+  }
+};
+
 // One wavefront per block; the wavefronts are independent. A wavefront
 // handles NC cells along x in each of its rows along y, one row per step.
 // DOT: each wavefront also writes the sum of x_i y_i over its cells (FP64,
 // fixed order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
-template <bool DOT>
-__device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, double* __restrict__ y,
+template <class Lanes, bool DOT>
+__device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restrict__ x, typename Lanes::T* __restrict__ y,
                                               const ScalarArgs<double>* __restrict__ ap,
                                               const uint32_t* __restrict__ waves, double* __restrict__ partial) {
+  using T = typename Lanes::T;
   __shared__ __attribute__((aligned(16))) double su[2 * NC * LCS];  // own cells of rows y and y + 1
   __shared__ __attribute__((aligned(16))) double sr[NC * LCS];      // x results, then x + y results
   const ScalarArgs<double>& a = *ap;
@@ -129,72 +358,41 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
   const int nsteps = min((int)(w1 >> 16), ny - ey0);
   const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
   const size_t row0 = (size_t)nx * ((size_t)ey0 + (size_t)ny * ez);
-  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;
+  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in values
   const bool hz0 = ez > 0, hz1 = ez < nz - 1;
-
-  const int h = lane & 1, t = (lane >> 1) & 3, pc = (lane >> 3) & 1, n = lane >> 4;
-  const int offz = 2 * h + 4 * t + 16 * n + 64 * pc;
+  // x layout: lane = i1 + 4 i2 + 16 i0, one cell per register
   const int offx = (lane >> 4) + 4 * (lane & 3) + 16 * ((lane >> 2) & 3);
-  const int lz = 2 * h + LIS * t + LPS * n + LCS * pc;
-  const int ly = 2 * h + LPS * t + LIS * n + LCS * pc;
   const int lx = (lane >> 4) + LIS * (lane & 3) + LPS * ((lane >> 2) & 3);
 
-  double2 rec[6];
-  const double2* lr = reinterpret_cast<const double2*>(a.lrec[lane]);
-#pragma unroll
-  for (int k = 0; k < 6; ++k) rec[k] = lr[k];
+  LineOps op;
+  const Lanes ln(lane, a, nvalid, op);
   const int ai = 4 * (lane & 3) + (lane >> 4);
   const uint32_t mask = a.mask;
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
-  const double Kx_int = rec[0].x, Lx = rec[0].y, Rx = rec[1].x;
-  const double Ky_int = rec[1].y;
-  const double Ly = rec[2].x, Ry = rec[2].y;
-  double Kz = rec[3].x;
-  const double Lz = rec[3].y, Rz = rec[4].x;
-  const double2 wn = rec[5];
-  if (vz != 0) Kz = a.Km[2][vz][ai];
+  const double Kz = vz != 0 ? a.Km[2][vz][ai] : op.Kz;
 
   // own row ey0 to buffer 0, row ey0 - 1 to buffer 1 (invalid or absent
   // cells as zeros)
-  {
-    const double* __restrict__ xc = x + (row0 + ex0) * 64;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const bool v = 2 * p + pc < nvalid;
-      const double2 u0 = load2(xc + 128 * p + offz, v);
-      const double2 um = load2(xc - sy + 128 * p + offz, v && ey0 > 0);
-      *reinterpret_cast<double2*>(su + 2 * LCS * p + lz) = u0;
-      *reinterpret_cast<double2*>(su + NC * LCS + 2 * LCS * p + lz) = um;
-    }
-  }
+  ln.first_rows(su, su + NC * LCS, x + (row0 + ex0) * 64, sy, nvalid, ey0 > 0);
 
   for (int s = 0; s < nsteps; ++s) {
     const int ey = ey0 + s;
     const bool hy0 = ey > 0, hy1 = ey < ny - 1;
     const size_t row = row0 + (size_t)s * nx;
-    const double* __restrict__ xc = x + (row + ex0) * 64;
-    double* cur = su + (s & 1) * (NC * LCS);  // row y
+    const T* __restrict__ xc = x + (row + ex0) * 64;
+    double* cur = su + (s & 1) * (NC * LCS);        // row y
     double* oth = su + ((s + 1) & 1) * (NC * LCS);  // row y - 1, then row y + 1
 
-    double2 nr[2], zl[2], zr[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const bool v = 2 * p + pc < nvalid;
-      const double* b = xc + 128 * p;
-      nr[p] = load2(b + sy + offz, v && hy1);
-      zl[p] = load2(b - sz + offz, v && hz0);
-      zr[p] = load2(b + sz + offz, v && hz1);
-    }
-    const double xl = hxl ? xc[offx - 64] : 0.0;
-    const double xr = hxr ? xc[64 * nvalid + offx] : 0.0;
+    const typename Lanes::Rows nr = ln.load_rows(xc, (int64_t)sy, nvalid, hy1);
+    const typename Lanes::Rows zl = ln.load_rows(xc, -(int64_t)sz, nvalid, hz0);
+    const typename Lanes::Rows zr = ln.load_rows(xc, (int64_t)sz, nvalid, hz1);
+    const double xl = hxl ? (double)xc[offx - 64] : 0.0;
+    const double xr = hxr ? (double)xc[64 * nvalid + offx] : 0.0;
 
     // row ey - 1 in the y layout, before the next row replaces it
-    double2 yl[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) yl[p] = *reinterpret_cast<const double2*>(oth + 2 * LCS * p + ly);
+    const typename Lanes::Rows yl = ln.lds_y(oth);
     __syncthreads();
-#pragma unroll
-    for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(oth + 2 * LCS * p + lz) = nr[p];
+    ln.store_z(oth, nr);
     __syncthreads();
     double ux[NC];
 #pragma unroll
@@ -207,72 +405,55 @@ __device__ __forceinline__ void apply_q3_wave(const double* __restrict__ x, doub
         const bool hx0 = ex > 0, hx1 = ex < nx - 1;
         const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
         const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
-        double Kx = Kx_int;
+        double Kx = op.Kx;
         if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
         double cx = mfma(Kx, ux[k], 0.0);
-        if (hx0) cx = mfma(Lx, ul, cx);
-        if (hx1) cx = mfma(Rx, ur, cx);
+        if (hx0) cx = mfma(op.Lx, ul, cx);
+        if (hx1) cx = mfma(op.Rx, ur, cx);
         sr[LCS * k + lx] = cx;
       }
     }
     __syncthreads();
     const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
-    const double Ky = vy != 0 ? a.Km[1][vy][ai] : Ky_int;
-    double2 uy[2], yr[2], uz[2];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      uy[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + ly);
-      yr[p] = *reinterpret_cast<const double2*>(oth + 2 * LCS * p + ly);
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (2 * p < nvalid) {
-        const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl[p], yr[p], hy0, hy1);
-        double2* r = reinterpret_cast<double2*>(sr + 2 * LCS * p + ly);
-        const double2 o = *r;
-        *r = make_double2(o.x + c.x, o.y + c.y);
-      }
-    }
+    const double Ky = vy != 0 ? a.Km[1][vy][ai] : op.Ky;
+    ln.y_stage(cur, oth, sr, yl, Ky, op.Ly, op.Ry, hy0, hy1, nvalid);
     __syncthreads();
-    double* __restrict__ yc = y + (row + ex0) * 64;
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      uz[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + lz);
-    }
-#pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      if (2 * p < nvalid) {
-        const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl[p], zr[p], hz0, hz1);
-        const double2 o = *reinterpret_cast<const double2*>(sr + 2 * LCS * p + lz);
-        if (2 * p + pc < nvalid) {
-          const dvec2 v = {wn.x * (o.x + c.x), wn.y * (o.y + c.y)};
-          __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(yc + 128 * p + offz));
-          if (DOT) pq = fma(uz[p].y, v.y, fma(uz[p].x, v.x, pq));
-        }
-      }
-    }
+    ln.template z_stage<DOT>(cur, sr, zl, zr, Kz, op.Lz, op.Rz, hz0, hz1, nvalid, y + (row + ex0) * 64, pq);
   }
-  if (DOT) {
+  if (DOT) {  // butterfly over the 64 lanes, then lane 0 writes
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) pq += __shfl_xor(pq, m, 64);
     if (lane == 0) partial[blockIdx.x] = pq;
   }
 }
 
-// The apply, with a register budget for five wavefronts per SIMD (93 VGPRs,
-// the matrix-core results in architectural VGPRs), and the conjugate-gradient
-// variant with the fused p.Ap.
+// The applies, with a register budget for five wavefronts per SIMD (the
+// matrix-core results in architectural VGPRs), and the conjugate-gradient
+// variants with the fused p.Ap.
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
     k_apply_q3_mfma(const double* __restrict__ x, double* __restrict__ y, const ScalarArgs<double>* __restrict__ ap,
                     const uint32_t* __restrict__ waves) {
-  apply_q3_wave<false>(x, y, ap, waves, nullptr);
+  apply_q3_wave<PairLanes, false>(x, y, ap, waves, nullptr);
 }
 
 __global__ void __launch_bounds__(64)
     k_apply_q3_mfma_dot(const double* __restrict__ x, double* __restrict__ y,
                         const ScalarArgs<double>* __restrict__ ap, const uint32_t* __restrict__ waves,
                         double* __restrict__ partial) {
-  apply_q3_wave<true>(x, y, ap, waves, partial);
+  apply_q3_wave<PairLanes, true>(x, y, ap, waves, partial);
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5)))
+    k_apply_q3_mfma_f32(const float* __restrict__ x, float* __restrict__ y,
+                        const ScalarArgs<double>* __restrict__ ap, const uint32_t* __restrict__ waves) {
+  apply_q3_wave<QuadLanes, false>(x, y, ap, waves, nullptr);
+}
+
+__global__ void __launch_bounds__(64)
+    k_apply_q3_mfma_f32_dot(const float* __restrict__ x, float* __restrict__ y,
+                            const ScalarArgs<double>* __restrict__ ap, const uint32_t* __restrict__ waves,
+                            double* __restrict__ partial) {
+  apply_q3_wave<QuadLanes, true>(x, y, ap, waves, partial);
 }
 
 // XCD-aware renumbering of hardware blocks (block b runs on XCD b % 8).
@@ -389,6 +570,24 @@ hipError_t mfma_build(dg_mesh& M, int prec, int rows) {
   M.nwaves[prec] = G;
   M.mfma_rows[prec] = rows;
   return hipSuccess;
+}
+
+bool mfma_apply_f32_supported(const dg_mesh& M, int prec, bool kappa) {
+  return M.p == 4 && prec == DG_F32 && !kappa && M.d_waves[DG_F32] != nullptr && !M.lines_forced[DG_F32];
+}
+
+hipError_t mfma_apply_f32(const dg_mesh& M, int variant, const float* x, float* y, double* partial,
+                          hipStream_t s) {
+  if (M.ndofs > 0xffffffffLL) return hipErrorInvalidValue;
+  const int64_t G = M.nwaves[DG_F32];
+  if (G < 1) return hipSuccess;
+  if (partial)
+    hipLaunchKernelGGL(k_apply_q3_mfma_f32_dot, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+                       (const uint32_t*)M.d_waves[DG_F32], partial);
+  else
+    hipLaunchKernelGGL(k_apply_q3_mfma_f32, dim3((unsigned)G), dim3(64), 0, s, x, y, M.d_pd + variant,
+                       (const uint32_t*)M.d_waves[DG_F32]);
+  return hipGetLastError();
 }
 
 hipError_t mfma_apply(const dg_mesh& M, int variant, const double* x, double* y, double* partial, hipStream_t s) {
