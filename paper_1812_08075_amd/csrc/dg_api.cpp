@@ -558,6 +558,7 @@ dg_status dg_mesh_destroy(dg_mesh* M) {
     if (M->d_vertices) (void)hipFree(M->d_vertices);
     if (M->d_gamma) (void)hipFree(M->d_gamma);
     if (M->d_cellgeo) (void)hipFree(M->d_cellgeo);
+    if (M->d_stokes_order) (void)hipFree(M->d_stokes_order);
     if (M->d_pd) (void)hipFree(M->d_pd);
     if (M->d_pf) (void)hipFree(M->d_pf);
     if (M->d_blocks) (void)hipFree(M->d_blocks);

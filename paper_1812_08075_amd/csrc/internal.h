@@ -184,6 +184,7 @@ struct dg_mesh {
   double* d_vertices = nullptr;   // device copy
   double* d_gamma = nullptr;      // per-face penalties [3][faces of direction d]
   double* d_cellgeo = nullptr;    // Stokes: coefficients of every cell's trilinear map
+  uint32_t* d_stokes_order = nullptr;  // Stokes: the cell of every block (sweep order)
   // parameter blocks of the diffusion-reaction kernels (host copies and device copies)
   dgi::ScalarArgs<double> pd[dgi::SP_COUNT]{};
   dgi::ScalarArgs<float> pf[dgi::SP_COUNT]{};

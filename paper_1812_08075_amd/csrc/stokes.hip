@@ -60,6 +60,7 @@ constexpr int NT = 64;
 constexpr int GEO = 24;  // doubles per cell of the geometry table: a1..a7, 3 components each, padded
 
 struct StokesGeom {
+  const uint32_t* order;  // cell of every block
   const double* cellgeo;  // GEO doubles per cell: a_m component k at 3 (m - 1) + k
   const double* gamma;    // per-face penalties, direction d at offset goff[d]
   int64_t goff[3];
@@ -145,7 +146,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   double* sRp = X + XR;
 
   const int t = threadIdx.x;
-  const int e = blockIdx.x;
+  const int e = (int)geo.order[blockIdx.x];  // the cell of this block (XCD-aware sweep table)
   const int nx = a.n[0], ny = a.n[1];
   const int ec[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
   const int64_t base = (int64_t)e * NB;
@@ -819,21 +820,50 @@ void stokes_setup(dg_mesh& M) {
       g[18 + k] = X[7][k] - X[6][k] - X[5][k] + X[4][k] - X[3][k] + X[2][k] + X[1][k] - X[0][k];
     }
   }
+  // Sweep order: the hardware dispatches block b to XCD b mod 8 and each XCD
+  // has its own L2. XCD x takes the x-th of 8 slabs of the mesh (along z, or
+  // along y when nz < 8), and inside a slab the cells run y-outermost, then z,
+  // then x, so that the cells in flight on an XCD and their y- and
+  // z-neighbours form a compact window of the slab.
+  const int64_t G = M.nelem;
+  std::vector<uint32_t> order;
+  order.reserve((size_t)G);
+  const bool zsplit = nz >= 8;
+  const int ns = zsplit ? nz : ny;
+  for (int r = 0; r < 8; ++r) {
+    const int s0 = (int)((int64_t)ns * r / 8), s1 = (int)((int64_t)ns * (r + 1) / 8);
+    const int z0 = zsplit ? s0 : 0, z1 = zsplit ? s1 : nz, y0 = zsplit ? 0 : s0, y1 = zsplit ? ny : s1;
+    for (int ey = y0; ey < y1; ++ey)
+      for (int ez = z0; ez < z1; ++ez)
+        for (int ex = 0; ex < nx; ++ex) order.push_back((uint32_t)(ex + (int64_t)nx * (ey + (int64_t)ny * ez)));
+  }
+  if ((int64_t)order.size() != G) throw std::runtime_error("Stokes sweep order");
+  std::vector<uint32_t> tab((size_t)G);
+  {
+    const int64_t q = G >> 3, rm = G & 7;
+    for (int64_t b = 0; b < G; ++b) {
+      const int64_t xcd = b & 7;
+      tab[(size_t)b] = order[(size_t)(xcd * q + std::min(xcd, rm) + (b >> 3))];
+    }
+  }
   if (hipMalloc(&M.d_vertices, sizeof(double) * M.vertices.size()) != hipSuccess ||
       hipMalloc(&M.d_gamma, sizeof(double) * gam.size()) != hipSuccess ||
-      hipMalloc(&M.d_cellgeo, sizeof(double) * cgeo.size()) != hipSuccess) {
+      hipMalloc(&M.d_cellgeo, sizeof(double) * cgeo.size()) != hipSuccess ||
+      hipMalloc(&M.d_stokes_order, sizeof(uint32_t) * tab.size()) != hipSuccess) {
     (void)hipGetLastError();
     throw std::runtime_error("device allocation failed (Stokes geometry)");
   }
   if (hipMemcpy(M.d_vertices, M.vertices.data(), sizeof(double) * M.vertices.size(), hipMemcpyHostToDevice) !=
           hipSuccess ||
       hipMemcpy(M.d_gamma, gam.data(), sizeof(double) * gam.size(), hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(M.d_cellgeo, cgeo.data(), sizeof(double) * cgeo.size(), hipMemcpyHostToDevice) != hipSuccess)
+      hipMemcpy(M.d_cellgeo, cgeo.data(), sizeof(double) * cgeo.size(), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(M.d_stokes_order, tab.data(), sizeof(uint32_t) * tab.size(), hipMemcpyHostToDevice) != hipSuccess)
     throw std::runtime_error("upload of the Stokes geometry failed");
 }
 
 hipError_t stokes_apply(const dg_mesh& M, const double* x, double* y, hipStream_t s) {
   StokesGeom g;
+  g.order = M.d_stokes_order;
   g.cellgeo = M.d_cellgeo;
   g.gamma = M.d_gamma;
   for (int d = 0; d < 3; ++d) g.goff[d] = M.gamma_off[d];
