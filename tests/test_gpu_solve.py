@@ -96,7 +96,9 @@ def test_kappa_solve(gpu_lib):
 
 @pytest.mark.parametrize("mode", [3, 4])  # DG_SOLVE_CHEB_F64, DG_SOLVE_CHEB_F32
 def test_chebyshev_with_kappa_per_point(gpu_lib, mode):
-    """kappa per quadrature point (log-normal, kappa traces on the faces): the
+    """kappa per quadrature point (log-normal in the cells, kappa = 1 on the
+    faces: with the trace reading the faces' kappa extrapolates to negative
+    values on this draw and A is indefinite, smallest eigenvalue -12.2): the
     Chebyshev steps after the first run fused into the line kernel with kappa
     (k = 4, no matrix-core kernel), in FP64 and on the FP32 operator with
     kappa rounded once; the solution reaches the oracle's residual."""
@@ -105,7 +107,7 @@ def test_chebyshev_with_kappa_per_point(gpu_lib, mode):
     N = (k + 1) ** 3
     kap = workloads.lognormal(n ** 3 * N, 5)
     print(f"case: Chebyshev mode {mode} with kappa per point, Q{k} {n}^3", flush=True)
-    mesh = dg.Mesh(dg.make_desc(n, k=k, kappa_mode=dg.DG_KAPPA_QP))
+    mesh = dg.Mesh(dg.make_desc(n, k=k, kappa_mode=dg.DG_KAPPA_QP, kappa_face=dg.DG_KAPPA_FACE_ONE))
     bh = workloads.uniform(n ** 3 * N, 6)
     b = torch.from_numpy(bh).cuda()
     kt = torch.from_numpy(kap).cuda()
@@ -115,7 +117,7 @@ def test_chebyshev_with_kappa_per_point(gpu_lib, mode):
     assert st == dg.DG_OK, dg.lib.dg_last_error()
     assert info.rel_residual <= 1e-10
     assert info.inner_applies == 5 * (info.iterations - 12 + info.outer)
-    A = ScalarDG(Problem(n, n, n, k=k, kappa=kap)).assemble("explicit")
+    A = ScalarDG(Problem(n, n, n, k=k, kappa=kap, kappa_face_one=True)).assemble("explicit")
     r = np.linalg.norm(bh - A.matvec(x.cpu().numpy())) / np.linalg.norm(bh)
     print(f"its={info.iterations} outer={info.outer} inner={info.inner_applies} oracle residual {r:.2e}")
     assert r <= 1.05e-10
