@@ -196,7 +196,8 @@ def cpu_model():
 
 def host_threads():
     """Threads the CPU baseline may use: the OpenMP setting of the host if any
-    (the GPU machine sets its CPU share there), else the CPUs this process may run on."""
+    (a shared host states the process's CPU share there), else the CPUs this
+    process may run on."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
