@@ -61,9 +61,13 @@ __device__ __forceinline__ T coord(const ScalarArgs<T>& a, int c, T xi, int d) {
 // ([own trace, neighbour trace, tangential test flux a, b] per side).
 // RESIDUAL adds the Dirichlet data terms of g. Called by every thread of the
 // block (it synchronizes twice); inactive threads pass active = false.
+// tD, tW, tX: the block's LDS copies of D, the weights and the nodes, for the
+// reads whose index depends on the thread (from the parameter block each such
+// read would be a vector load of its own).
 template <int P, typename T, bool RESIDUAL, int DIR>
 __device__ __forceinline__ void tensor_faces(const ScalarArgs<T>& a, bool active, const T* v, const T (*nb)[P],
-                                             const bool* has, const int* cc, int ta, int tb, T* fb, T* out) {
+                                             const bool* has, const int* cc, int ta, int tb, T* fb, T* out,
+                                             const T* tD, const T* tW, const T* tX) {
   constexpr int L = P * P;
   constexpr int DA = DIR == 0 ? 1 : 0, DB = DIR == 2 ? 1 : 2;  // tangential directions
   const int pt = ta + P * tb;
@@ -91,10 +95,10 @@ __device__ __forceinline__ void tensor_faces(const ScalarArgs<T>& a, bool active
   T Rv[2] = {T(0), T(0)}, Rd[2] = {T(0), T(0)};
   if (active) {
     const T ha_inv = a.hinv[DA], hb_inv = a.hinv[DB], hd_inv = a.hinv[DIR];
-    const T wF = a.w[ta] * a.w[tb] * a.fs[DIR];  // tangential weights x |F| / reference area
+    const T wF = tW[ta] * tW[tb] * a.fs[DIR];  // tangential weights x |F| / reference area
     T xF[3];
-    xF[DA] = coord(a, cc[DA], a.xi[ta], DA);
-    xF[DB] = coord(a, cc[DB], a.xi[tb], DB);
+    xF[DA] = coord(a, cc[DA], tX[ta], DA);
+    xF[DB] = coord(a, cc[DB], tX[tb], DB);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       T Ra = T(0), Rb = T(0);
@@ -107,8 +111,8 @@ __device__ __forceinline__ void tensor_faces(const ScalarArgs<T>& a, bool active
         T ga = T(0), gb = T(0);
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-          ga = fma(a.D[ta * P + j], fo[j + P * tb], ga);
-          gb = fma(a.D[tb * P + j], fo[ta + P * j], gb);
+          ga = fma(tD[ta * P + j], fo[j + P * tb], ga);
+          gb = fma(tD[tb * P + j], fo[ta + P * j], gb);
         }
         T g[3];
         g[DIR] = No[s] * hd_inv;
@@ -125,8 +129,8 @@ __device__ __forceinline__ void tensor_faces(const ScalarArgs<T>& a, bool active
           T na = T(0), nbt = T(0);
 #pragma unroll
           for (int j = 0; j < P; ++j) {
-            na = fma(a.D[ta * P + j], fn[j + P * tb], na);
-            nbt = fma(a.D[tb * P + j], fn[ta + P * j], nbt);
+            na = fma(tD[ta * P + j], fn[j + P * tb], na);
+            nbt = fma(tD[tb * P + j], fn[ta + P * j], nbt);
           }
           T h[3];
           h[DIR] = Nn[s] * hd_inv;
@@ -167,8 +171,8 @@ __device__ __forceinline__ void tensor_faces(const ScalarArgs<T>& a, bool active
       T tt = Rv[s];
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        tt = fma(a.D[j * P + ta], ra[j + P * tb], tt);
-        tt = fma(a.D[j * P + tb], rb[ta + P * j], tt);
+        tt = fma(tD[j * P + ta], ra[j + P * tb], tt);
+        tt = fma(tD[j * P + tb], rb[ta + P * j], tt);
       }
 #pragma unroll
       for (int i = 0; i < P; ++i) out[i] = fma(a.e[s][i], tt, fma(a.de[s][i], Rd[s], out[i]));
@@ -191,6 +195,7 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
   __shared__ T g1[EB * Ly::NP];  // d_1 u, then the flux component 1
   __shared__ T sy[EB * Ly::NP];  // x-line results, += y-line results
   __shared__ T sf[EB * 8 * L];   // face buffers
+  __shared__ T tD[P * P], tW[P], tX[P];  // D, weights, nodes (reads indexed by the thread's line)
 
   const BlockCoord bc = block_coord(blocks);
   const int nx = a.n[0], ny = a.n[1], nz = a.n[2];
@@ -206,6 +211,11 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
   const uint32_t e = row + ex;
   const int cc[3] = {ex, bc.ey, bc.ez};
   if (active) load_cell_column<P, T>(su, x, gbase, le, ta, tb);
+  if (threadIdx.x < P * P) tD[threadIdx.x] = a.D[threadIdx.x];
+  if (threadIdx.x < P) {
+    tW[threadIdx.x] = a.w[threadIdx.x];
+    tX[threadIdx.x] = a.xi[threadIdx.x];
+  }
   __syncthreads();
   const T* sue = su + le * Ly::NP;
   T* fb = sf + le * 8 * L;
@@ -239,8 +249,8 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
   T rz[P], oz[P];
   if (active) {
     const T detJ = a.vs[0] / (a.hinv[0] * a.hinv[0]);
-    const T w01 = a.w[ta] * a.w[tb];
-    const T x0 = coord(a, ex, a.xi[ta], 0), x1 = coord(a, bc.ey, a.xi[tb], 1);
+    const T w01 = tW[ta] * tW[tb];
+    const T x0 = coord(a, ex, tX[ta], 0), x1 = coord(a, bc.ey, tX[tb], 1);
     T* g0e = g0 + le * Ly::NP + ta + Ly::S1 * tb;
     T* g1e = g1 + le * Ly::NP + ta + Ly::S1 * tb;
 #pragma unroll
@@ -275,7 +285,7 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
       }
       neighbor_lines<P, T, 0>(su, x, e, le, nvalid, ex, nx, 1u, ta, tb, nb, has);
     }
-    tensor_faces<P, T, RESIDUAL, 0>(a, active, vx, nb, has, cc, ta, tb, fb, o);
+    tensor_faces<P, T, RESIDUAL, 0>(a, active, vx, nb, has, cc, ta, tb, fb, o, tD, tW, tX);
     if (active) lds_store_line<P, T, 0>(sy + le * Ly::NP, ta, tb, o);
   }
   {  // y
@@ -293,7 +303,7 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
       neighbor_lines<P, T, 1>(su, x, e, le, nvalid, bc.ey, ny, (uint32_t)nx, ta, tb, nb, has);
     }
     // the faces synchronize before the update below, after the x results are stored
-    tensor_faces<P, T, RESIDUAL, 1>(a, active, vy, nb, has, cc, ta, tb, fb, o);
+    tensor_faces<P, T, RESIDUAL, 1>(a, active, vy, nb, has, cc, ta, tb, fb, o, tD, tW, tX);
     if (active) {
 #pragma unroll
       for (int i = 0; i < P; ++i) sy[le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb] += o[i];
@@ -310,7 +320,7 @@ __global__ void __launch_bounds__(TensorCells<P>::value * P * P)
       }
       neighbor_lines<P, T, 2>(su, x, e, le, nvalid, bc.ez, nz, (uint32_t)nx * ny, ta, tb, nb, has);
     }
-    tensor_faces<P, T, RESIDUAL, 2>(a, active, vz, nb, has, cc, ta, tb, fb, oz);
+    tensor_faces<P, T, RESIDUAL, 2>(a, active, vz, nb, has, cc, ta, tb, fb, oz, tD, tW, tX);
     if (active) {
       const int lo = le * Ly::NP + ta + Ly::S1 * tb;
       T* __restrict__ ye = y + e * N + ta + P * tb;
