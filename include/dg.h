@@ -128,20 +128,22 @@ typedef struct {
   int32_t precond;          /* DG_PRECOND_*: preconditioner of every CG in the solve (FP64 CG
                                and the FP32 inner CG alike; CHEB: of the Chebyshev iteration) */
   int32_t cheb_degree;      /* CHEB: steps s of the inner Chebyshev iteration, 1..64 (0 -> 8) */
-  int32_t cheb_lanczos;     /* CHEB: CG iterations whose Lanczos coefficients estimate the
-                               largest eigenvalue, 2..64 (0 -> 20) */
+  int32_t cheb_lanczos;     /* CHEB: CG iterations on a pseudo-random right-hand side whose
+                               Lanczos coefficients estimate the largest eigenvalue, 2..64 (0 -> 20) */
   double cheb_ratio;        /* CHEB: b / a of the Chebyshev interval [a, b], > 1 (0 -> max(s^2, 16)) */
   double cheb_margin;       /* CHEB: b = margin x the largest Ritz value, >= 1 (0 -> 1.1) */
 } dg_solve_params;
 
 typedef struct {
-  int32_t iterations;       /* CG iterations (FP64 CG; CHEB: FP64 CG iterations including the
-                               estimate) or total inner iterations (IR, RU) */
+  int32_t iterations;       /* CG iterations (FP64 CG; CHEB: FP64 CG iterations, the first
+                               cheb_lanczos unpreconditioned by the polynomial included)
+                               or total inner iterations (IR, RU) */
   int32_t outer;            /* refinement steps / residual replacements (0 for FP64 CG) */
   double rel_residual;      /* true ||b - A x||_2 / ||b||_2 in FP64 at exit */
   double seconds;           /* wall time of the solve, host clock */
   int32_t inner_applies;    /* CHEB: operator applies of the inner Chebyshev iterations */
-  int32_t pad;
+  int32_t lanczos_iterations; /* CHEB: CG iterations on the pseudo-random right-hand side
+                                 (the estimate's own, not in iterations) */
   double lambda_max;        /* CHEB: the largest Ritz value of the estimate (of P A, or of A) */
 } dg_solve_info;
 
@@ -214,9 +216,13 @@ dg_status dg_precond_apply(const dg_mesh* mesh, int precision, const void* r, vo
  *    applies; with the block-Jacobi preconditioner P, the Chebyshev
  *    iteration of P A). The iteration has no inner products, so FP32
  *    rounding does not accumulate through a Krylov recursion. Its interval
- *    [b / cheb_ratio, b] comes from b = cheb_margin x the largest Ritz value
- *    of the Lanczos coefficients of the first cheb_lanczos FP64 CG
- *    iterations, which the solve runs first (they advance x as well).
+ *    [b / cheb_ratio, b] comes from b = cheb_margin x the larger of two
+ *    largest Ritz values: of cheb_lanczos (P)CG iterations in the inner
+ *    precision on a fixed pseudo-random right-hand side (every eigenvector
+ *    present: started from a smooth b alone the Krylov space can miss the
+ *    top of the spectrum, and an even-degree polynomial is then indefinite
+ *    there), and of the first cheb_lanczos FP64 (P)CG iterations of the
+ *    solve (which advance x as well).
  *  DG_SOLVE_CHEB_F64: the same with the inner iteration in FP64 (the
  *    baseline that isolates the gain of the FP32 inner work).
  * b, x: device FP64 vectors; x holds the initial guess on entry. kappa as in

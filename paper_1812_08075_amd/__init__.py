@@ -64,7 +64,8 @@ class dg_solve_params(ctypes.Structure):
 class dg_solve_info(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("outer", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("seconds", ctypes.c_double),
-                ("inner_applies", ctypes.c_int32), ("pad", ctypes.c_int32), ("lambda_max", ctypes.c_double)]
+                ("inner_applies", ctypes.c_int32), ("lanczos_iterations", ctypes.c_int32),
+                ("lambda_max", ctypes.c_double)]
 
 
 DG_VARIANT_MATRIX_CORE, DG_VARIANT_LINES = 0, 1

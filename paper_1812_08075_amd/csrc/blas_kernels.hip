@@ -271,6 +271,20 @@ __global__ void __launch_bounds__(RT) k_round_f32(const double* __restrict__ a, 
   for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) b[i] = (float)a[i];
 }
 
+// a[i] = a pseudo-random value in [-1, 1) from the counter i and the seed:
+// the SplitMix64 output function (Steele, Lea and Flood, 2014) of
+// seed + (i + 1) times the golden-ratio increment, top 53 bits.
+template <typename T>
+__global__ void __launch_bounds__(RT) k_random(T* __restrict__ a, int64_t n, uint64_t seed) {
+  for (int64_t i = (int64_t)blockIdx.x * RT + threadIdx.x; i < n; i += (int64_t)gridDim.x * RT) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    a[i] = (T)(2.0 * ((double)(z >> 11) * 0x1.0p-53) - 1.0);
+  }
+}
+
 // Sets the scalars of a fresh CG run (r.r taken from nrm2 or 1 for the
 // normalized inner right-hand side).
 __global__ void k_state_reset(CgState* st, int from_norm) {
@@ -415,6 +429,14 @@ hipError_t blas_round_f32(const double* a, float* b, int64_t n, hipStream_t s) {
 
 hipError_t blas_widen(const float* a, double* b, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(k_widen, dim3(grid_for(n)), dim3(RT), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+hipError_t blas_random(void* a, int prec, int64_t n, uint64_t seed, hipStream_t s) {
+  if (prec == DG_F64)
+    hipLaunchKernelGGL(k_random<double>, dim3(grid_for(n)), dim3(RT), 0, s, (double*)a, n, seed);
+  else
+    hipLaunchKernelGGL(k_random<float>, dim3(grid_for(n)), dim3(RT), 0, s, (float*)a, n, seed);
   return hipGetLastError();
 }
 

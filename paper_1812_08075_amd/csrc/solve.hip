@@ -166,7 +166,7 @@ size_t layout(const dg_mesh& M, int mode, bool pc, bool kap, char* base, Work* w
     w->p = (double*)take(sizeof(double) * n);
     if (pc) w->z = (double*)take(sizeof(double) * n);
   } else if (cheb_mode(mode)) {
-    w->hist = (double*)take(sizeof(double) * 2 * kMaxLanczos);
+    w->hist = (double*)take(sizeof(double) * 4 * kMaxLanczos);  // two runs of (alpha, beta)
     w->p = (double*)take(sizeof(double) * n);
     if (pc || mode == DG_SOLVE_CHEB_F64) w->z = (double*)take(sizeof(double) * n);
     if (mode == DG_SOLVE_CHEB_F64) {
@@ -346,7 +346,7 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
   info->rel_residual = 0.0;
   info->seconds = 0.0;
   info->inner_applies = 0;
-  info->pad = 0;
+  info->lanczos_iterations = 0;
   info->lambda_max = 0.0;
   dg_status status = DG_OK;
   if (bnorm == 0.0) {
@@ -394,22 +394,52 @@ dg_status run(const dg_mesh* M, int mode, const double* b, double* x, const void
     const bool fused = !dgi::mfma_apply_supported(*M, ip, kapc != nullptr) &&
                        !dgi::mfma_apply_f32_supported(*M, ip, kapc != nullptr);
     int total = 0, applies = 0, outer = 0;
-    // 1. the first FP64 (P)CG iterations, recording their Lanczos coefficients
+    // 1. the spectrum, from two Lanczos matrices: (a) nlz (P)CG iterations in
+    // the inner precision on a fixed pseudo-random right-hand side (every
+    // eigenvector present; the iterate is not kept: the buffer of A p stands
+    // in for it, its update landing after A p has been used), (b) the first
+    // nlz FP64 (P)CG iterations of the solve itself (they advance x). From a
+    // smooth b alone the Krylov space can miss the top of the spectrum, and a
+    // polynomial of even degree is not positive above b; from the random start
+    // alone the outer CG would begin on the raw residual, which the FP32 inner
+    // iteration serves worse. Both Ritz values lie below the largest
+    // eigenvalue; the larger one sets the interval.
+    {
+      void* er = f32 ? (void*)w.f[0] : (void*)r;
+      void* ep = f32 ? (void*)w.f[2] : (void*)p;
+      void* eq = f32 ? (void*)w.f[3] : (void*)q;
+      void* ez = f32 ? (void*)w.f[1] : (void*)zv;
+      ck(dgi::blas_random(er, ip, n, 0x2545F4914F6CDD1Dull, s), "random right-hand side");
+      ck(dgi::blas_dot(er, er, ip, n, S.partial(), S.st(), dgi::OP_NORM, s), "r.r");
+      ck(dgi::blas_state_from_norm(S.st(), s), "state");
+      S.start_direction(ip, er, ep, ez);
+      for (int j = 0; j < nlz; ++j) {
+        S.iterate(ip, eq, er, ep, eq, ez, kapc);
+        ck(dgi::blas_record(S.st(), w.hist, j, s), "record");
+      }
+    }
+    info->lanczos_iterations = nlz;
+    // r = b - A x again (in FP64 mode the estimate ran in r's buffer)
+    (void)S.true_residual(b, x, r, q);
     ck(dgi::blas_state_from_norm(S.st(), s), "state");
     S.start_direction(DG_F64, r, p, zv);
     int nrec = 0;
     for (; nrec < nlz && total < prm->maxit; ++nrec, ++total) {
       S.iterate(DG_F64, x, r, p, q, zv, kappa);
-      ck(dgi::blas_record(S.st(), w.hist, nrec, s), "record");
+      ck(dgi::blas_record(S.st(), w.hist, nlz + nrec, s), "record");
     }
-    double hist[2 * kMaxLanczos];
-    ck(hipMemcpyAsync(hist, w.hist, sizeof(double) * 2 * nrec, hipMemcpyDeviceToHost, s), "Lanczos readback");
+    double hist[4 * kMaxLanczos];
+    ck(hipMemcpyAsync(hist, w.hist, sizeof(double) * 2 * (nlz + nrec), hipMemcpyDeviceToHost, s),
+       "Lanczos readback");
     (void)S.read();  // also waits for the coefficients
-    // a CG that converged (or broke down) within these iterations leaves a
-    // zero step length behind: the estimate uses the iterations before it
-    int nval = 0;
-    while (nval < nrec && hist[2 * nval] > 0.0 && std::isfinite(hist[2 * nval])) ++nval;
-    const double lmax = nval >= 1 ? lanczos_max(hist, nval) : 0.0;
+    // a CG that converged (or broke down) within its iterations leaves a zero
+    // step length behind: each estimate uses the iterations before it
+    auto ritz_max = [&](const double* h, int k) {
+      int nval = 0;
+      while (nval < k && h[2 * nval] > 0.0 && std::isfinite(h[2 * nval])) ++nval;
+      return nval >= 1 ? lanczos_max(h, nval) : 0.0;
+    };
+    const double lmax = std::max(ritz_max(hist, nlz), ritz_max(hist + 2 * nlz, nrec));
     info->lambda_max = lmax;
     res = std::sqrt(S.true_residual(b, x, r, q));
     if (res > target && !(lmax > 0.0)) breakdown = 1;

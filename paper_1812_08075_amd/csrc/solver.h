@@ -77,5 +77,7 @@ hipError_t blas_record(const CgState* st, double* hist, int j, hipStream_t s);
 hipError_t blas_state_zero(CgState* st, hipStream_t s);
 // rr = rr0 = nrm2, alpha = beta = 0.
 hipError_t blas_state_from_norm(CgState* st, hipStream_t s);
+// a = pseudo-random values in [-1, 1), a function of the index and the seed only.
+hipError_t blas_random(void* a, int prec, int64_t n, uint64_t seed, hipStream_t s);
 
 }  // namespace dgi

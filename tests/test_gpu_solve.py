@@ -231,8 +231,37 @@ def test_chebyshev_pcg_matches_direct_solve(gpu_lib, mode, wid, pc):
           f"|x-x_direct|={err:.2e}")
     assert err < 1e-6
     assert info.lambda_max > 0
-    # 12 plain CG iterations, then 4 applies per preconditioned iteration
+    # the estimate: 12 CG iterations on the pseudo-random right-hand side and
+    # the first 12 CG iterations of the solve; then 4 applies per
+    # preconditioner application (one per CG iteration and one per start of
+    # the outer CG)
+    assert info.lanczos_iterations == 12
     assert info.inner_applies == 4 * (info.iterations - 12 + info.outer)
+
+
+@pytest.mark.parametrize("deg", [1, 2, 3])
+@pytest.mark.parametrize("pc", [0, 1])
+def test_chebyshev_low_degrees(gpu_lib, deg, pc):
+    """The shortest polynomials: s = 1 (the first step is the last: no fused
+    step, c2 = 1/theta times r or P r), s = 2 (the one fused step is the last,
+    which reduces r.z) and s = 3; FP32 inner iteration on Q5 (line kernels).
+    Even degrees need the top of the spectrum below b: estimated from the
+    smooth right-hand side alone, lambda_max came out 12.9 against the true
+    20.8 here and the s = 2 and 4 solves stalled (a pseudo-random right-hand
+    side now takes part in the estimate)."""
+    dg = gpu_lib
+    w = workloads.WORKLOADS[5]
+    n = 3
+    print(f"case: Chebyshev degree {deg} precond {pc} {w.name} {n}^3", flush=True)
+    mesh, b = setup(dg, w, n)
+    x = torch.zeros_like(b)
+    st, info = dg.dg_solve(mesh.handle, 4, b, x, rtol=1e-10, maxit=20000, precond=pc, cheb_degree=deg,
+                           cheb_lanczos=10)
+    assert st == dg.DG_OK, dg.lib.dg_last_error()
+    assert info.inner_applies == (deg - 1) * (info.iterations - 10 + info.outer)
+    A = ScalarDG(problem_from_workload(w, n=n)).assemble()
+    bh = b.cpu().numpy()
+    assert np.linalg.norm(bh - A.matvec(x.cpu().numpy())) <= 1.05e-10 * np.linalg.norm(bh)
 
 
 def test_chebyshev_lanczos_estimate_brackets_the_spectrum(gpu_lib):
