@@ -78,7 +78,7 @@ __device__ __forceinline__ int pnode(int d, int jd, int ja, int jb) {
   return i0 + KP * (i1 + KP * i2);
 }
 
-__host__ __device__ __forceinline__ void face_dirs(int d, int& t1, int& t2) {
+__device__ __forceinline__ void face_dirs(int d, int& t1, int& t2) {
   t1 = d == 0 ? 1 : 0;
   t2 = d == 2 ? 1 : 2;
 }
@@ -150,7 +150,6 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   const int nx = a.n[0], ny = a.n[1];
   const int ec[3] = {e % nx, (e / nx) % ny, e / (nx * ny)};
   const int64_t base = (int64_t)e * NB;
-  const int64_t estr[3] = {1, nx, (int64_t)nx * ny};
   unsigned hasn = 0;  // bit f: face f has a neighbour
 #pragma unroll
   for (int f = 0; f < 6; ++f) {
@@ -160,7 +159,6 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   }
   auto has_nb_of = [&](int f) { return ((hasn >> f) & 1u) != 0; };
   auto ecd = [&](int d) { return d == 0 ? ec[0] : (d == 1 ? ec[1] : ec[2]); };
-  auto estrd = [&](int d) { return d == 0 ? estr[0] : (d == 1 ? estr[1] : estr[2]); };
   // the cell across face f (lane-varying f: a chain of selects of uniform values)
   const int nxy = nx * ny;
   auto nb_of = [&](int f) -> int64_t {
