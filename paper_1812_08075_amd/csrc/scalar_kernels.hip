@@ -546,9 +546,11 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
   using Ly = Layout<P>;
   static_assert(EB * Ly::NP * sizeof(T) >= 256 * sizeof(double), "reduction scratch");
   static_assert(!(EPI == EPI_CHEB_BJ && KAPPA), "the block-Jacobi inverse is built for kappa = 1");
-  __shared__ T sx[EB * Ly::NP];
+  // the chunk's cells; once every line has been read, the x-line results,
+  // then += the y-line results (each thread keeps its own z-line, the cell
+  // column it stands for, in registers)
+  __shared__ __attribute__((aligned(16))) T sx[EB * Ly::NP];
   __shared__ T sk[KAPPA ? EB * Ly::NP : 1];
-  __shared__ __attribute__((aligned(16))) T sy[EB * Ly::NP];  // x-line results, then += y-line results
   __shared__ T sV[EPI == EPI_CHEB_BJ ? 3 * L : 1], sL[EPI == EPI_CHEB_BJ ? 3 * P : 1];
 
   const BlockCoord bc = block_coord(a.blocks);
@@ -592,6 +594,7 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     }
   }
   T out0[P], out1[P], out2[P];
+  T vz[P];  // the thread's own z-line: the input column (ta, tb, 0..P-1)
   if (work) {
     T v[P], kv[P];
     T nb[2][P], nk[2][P];
@@ -610,28 +613,29 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       neighbor_lines<P, T, 1>(sk, kappa, e, le, nvalid, active ? bc.ey : 0, active ? ny : 1, (uint32_t)nx, ta, tb, nk1,
                               has1);
     line_work<P, T, KAPPA, 1, MC>(v, kv, nb1, nk1, has1, a, false, AD, ADt, out1);
-    if (active) {
+    lds_line<P, T, 2>(sxe, ta, tb, vz);
+  }
+  __syncthreads();  // every line of the cells has been read: sx takes the results
+  if (work && active) {
 #pragma unroll
-      for (int i = 0; i < P; ++i) sy[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
-    }
+    for (int i = 0; i < P; ++i) sx[le * Ly::NP + i + Ly::S1 * ta + Ly::S2 * tb] = wt * out0[i];
   }
   __syncthreads();
   if (work) {
     if (active) {
 #pragma unroll
       for (int i = 0; i < P; ++i) {
-        T* yi = sy + le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
+        T* yi = sx + le * Ly::NP + ta + Ly::S1 * i + Ly::S2 * tb;
         *yi = fma(wt, out1[i], *yi);
       }
     }
     // lines along z: (i0, i1) = (ta, tb), kept in registers
-    T v[P], kv[P];
-    lds_line<P, T, 2>(sxe, ta, tb, v);
+    T kv[P];
     if (KAPPA) lds_line<P, T, 2>(ske, ta, tb, kv);
     neighbor_lines<P, T, 2>(sx, x, e, le, nvalid, active ? bc.ez : 0, active ? nz : 1, nxy, ta, tb, nb2, has2);
     if (KAPPA)
       neighbor_lines<P, T, 2>(sk, kappa, e, le, nvalid, active ? bc.ez : 0, active ? nz : 1, nxy, ta, tb, nk2, has2);
-    line_work<P, T, KAPPA, 2, MC>(v, kv, nb2, nk2, has2, a, false, AD, ADt, out2);
+    line_work<P, T, KAPPA, 2, MC>(vz, kv, nb2, nk2, has2, a, false, AD, ADt, out2);
   }
   __syncthreads();
   double pq = 0.0;
@@ -641,14 +645,14 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       T* __restrict__ ye = y + e * N + ta + P * tb;
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const T v = fma(wt, out2[j], sy[lo + j * Ly::S2]);
+        const T v = fma(wt, out2[j], sx[lo + j * Ly::S2]);
         ye[j * L] = v;
-        if (DOT) pq = fma((double)sx[lo + j * Ly::S2], (double)v, pq);
+        if (DOT) pq = fma((double)vz[j], (double)v, pq);
       }
     }
   } else {
-    // the Chebyshev step on the thread's column (ta, tb, 0..P-1): it reads its
-    // own column of z from sx before the preconditioner overwrites it there
+    // the Chebyshev step on the thread's column (ta, tb, 0..P-1): A z from sx,
+    // z itself from the registers (the preconditioner then uses sx as scratch)
     const int lo = le * Ly::NP + ta + Ly::S1 * tb;
     const size_t col = (size_t)e * N + ta + P * tb;
     T w[P], zv[P], o[P];
@@ -657,8 +661,8 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
     if (active) {
 #pragma unroll
       for (int j = 0; j < P; ++j) {
-        const T t = fma(wt, out2[j], sy[lo + j * Ly::S2]);
-        zv[j] = sx[lo + j * Ly::S2];
+        const T t = fma(wt, out2[j], sx[lo + j * Ly::S2]);
+        zv[j] = vz[j];
         const T ri = cs.rd ? (T)cs.rd[col + (size_t)j * L] : cs.r[col + (size_t)j * L];
         w[j] = ri - t;
       }
@@ -681,12 +685,12 @@ __global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
       }
     }
     if (cs.last && cs.rd) {
-      __syncthreads();  // sy becomes the reduction scratch
-      block_sum_to<NT>(pq, reinterpret_cast<double*>(sy), partial, chunk_slot(bc, a, EB));
+      __syncthreads();  // sx becomes the reduction scratch
+      block_sum_to<NT>(pq, reinterpret_cast<double*>(sx), partial, chunk_slot(bc, a, EB));
     }
   }
-  if (DOT) {  // fixed-order tree over the block (NT in [128, 256]), sy as scratch
-    double* sh = reinterpret_cast<double*>(sy);
+  if (DOT) {  // fixed-order tree over the block (NT in [128, 256]), sx as scratch
+    double* sh = reinterpret_cast<double*>(sx);
     __syncthreads();
     if (threadIdx.x + NT < 256) sh[threadIdx.x + NT] = 0.0;
     sh[threadIdx.x] = pq;
