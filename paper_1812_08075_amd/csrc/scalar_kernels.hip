@@ -907,7 +907,7 @@ __global__ void __launch_bounds__(AdjCellsPerBlock<P>::value * P * P)
 // read from device memory), and partial sums of r.r go to partial_rr: one
 // pass over r, q and z per conjugate-gradient iteration.
 template <int P, typename T>
-__global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P)
+__global__ void __launch_bounds__(CellsPerBlock<P>::value * P * P) __attribute__((amdgpu_waves_per_eu(4)))
     k_block_jacobi(T* __restrict__ r, T* __restrict__ z, const ScalarArgs<T>* __restrict__ ap,
                    double* __restrict__ partial, const T* __restrict__ q, const double* __restrict__ alpha,
                    double* __restrict__ partial_rr) {
