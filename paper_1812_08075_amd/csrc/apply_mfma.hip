@@ -40,8 +40,11 @@
 //    layout, into the buffer that held row y - 1), the z-neighbour cells
 //    and the two x-end lines; the y-neighbour lines come from LDS, row
 //    y - 1 read before it is replaced. That is 8 global loads per 4 cells
-//    where reading the y-neighbours from L2 takes 12, and the load issue
-//    rate, not the bytes, is what limits this kernel. The A-operand entries
+//    where reading the y-neighbours from L2 takes 12 (the load issue rate
+//    bounded the kernel that read them from L2). Marches of odd
+//    y-blocks run downwards (mirror image: the row behind is y + 1), so
+//    that two neighbouring marches reach the rows of their shared boundary
+//    at the same time. The A-operand entries
 //    of the nine interior-cell operators and the two nodes' tensor weights
 //    form one 96-byte record per lane, read once per wavefront; boundary
 //    cells and rows read their own K variant. Wavefronts are independent
@@ -198,14 +201,15 @@ struct PairLanes {
     op = LineOps{rec[0].x, rec[0].y, rec[1].x, rec[1].y, rec[2].x, rec[2].y, rec[3].x, rec[3].y, rec[4].x};
     wn = rec[5];
   }
-  // rows y (buffer cur) and y - 1 (buffer oth) of the chunk at xc
-  __device__ __forceinline__ void first_rows(double* cur, double* oth, const double* xc, size_t sy, int nvalid,
+  // the first row of the march (buffer cur) and the row behind it, at
+  // offset back (buffer oth), of the chunk at xc
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const double* xc, int64_t back, int nvalid,
                                              bool has_prev) const {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const bool v = 2 * p + pc < nvalid;
       const double2 u0 = load2(xc + 128 * p + offz, v);
-      const double2 um = load2(xc - sy + 128 * p + offz, v && has_prev);
+      const double2 um = load2(xc + back + 128 * p + offz, v && has_prev);
       *reinterpret_cast<double2*>(cur + 2 * LCS * p + lz) = u0;
       *reinterpret_cast<double2*>(oth + 2 * LCS * p + lz) = um;
     }
@@ -226,8 +230,11 @@ struct PairLanes {
 #pragma unroll
     for (int p = 0; p < 2; ++p) *reinterpret_cast<double2*>(b + 2 * LCS * p + lz) = r.v[p];
   }
-  // sr += the y lines of row cur (neighbours yl and the row in oth)
-  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yl, double Ky,
+  // sr += the y lines of row cur; neighbours: yb (the row behind) and the
+  // row in oth (the row ahead), on the y - 1 and y + 1 sides for an upward
+  // march and the other way round for a downward one
+  template <bool DOWN>
+  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yb, double Ky,
                                           double Ly, double Ry, bool hy0, bool hy1, int nvalid) const {
     double2 uy[2], yr[2];
 #pragma unroll
@@ -238,7 +245,8 @@ struct PairLanes {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       if (2 * p < nvalid) {
-        const double2 c = pair_line(Ky, Ly, Ry, uy[p], yl.v[p], yr[p], hy0, hy1);
+        const double2 c = DOWN ? pair_line(Ky, Ly, Ry, uy[p], yr[p], yb.v[p], hy0, hy1)
+                               : pair_line(Ky, Ly, Ry, uy[p], yb.v[p], yr[p], hy0, hy1);
         double2* r = reinterpret_cast<double2*>(sr + 2 * LCS * p + ly);
         const double2 o = *r;
         *r = make_double2(o.x + c.x, o.y + c.y);
@@ -291,19 +299,22 @@ struct QuadLanes {
 #pragma unroll
     for (int q = 0; q < 4; ++q) wq[q] = a.lrec[(q >> 1) + 2 * zi1 + 16 * zi2][10 + (q & 1)];
   }
-  __device__ __forceinline__ void first_rows(double* cur, double* oth, const float* xc, size_t sy, int,
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const float* xc, int64_t back, int,
                                              bool has_prev) const {
     lds_store_quad(cur + lz, load_quad(xc + offz, cok));
-    lds_store_quad(oth + lz, load_quad(xc - sy + offz, cok && has_prev));
+    lds_store_quad(oth + lz, load_quad(xc + back + offz, cok && has_prev));
   }
   __device__ __forceinline__ Rows load_rows(const float* xc, int64_t off, int, bool ok) const {
     return load_quad(xc + off + offz, cok && ok);
   }
   __device__ __forceinline__ Rows lds_y(const double* b) const { return lds_quad(b + ly); }
   __device__ __forceinline__ void store_z(double* b, const Rows& r) const { lds_store_quad(b + lz, r); }
-  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yl, double Ky,
+  template <bool DOWN>
+  __device__ __forceinline__ void y_stage(const double* cur, const double* oth, double* sr, const Rows& yb, double Ky,
                                           double Ly, double Ry, bool hy0, bool hy1, int) const {
-    const Quad cy = quad_line(Ky, Ly, Ry, lds_quad(cur + ly), yl, lds_quad(oth + ly), hy0, hy1);
+    const Quad ya = lds_quad(oth + ly);
+    const Quad cy = DOWN ? quad_line(Ky, Ly, Ry, lds_quad(cur + ly), ya, yb, hy0, hy1)
+                         : quad_line(Ky, Ly, Ry, lds_quad(cur + ly), yb, ya, hy0, hy1);
     Quad o = lds_quad(sr + ly);
 #pragma unroll
     for (int q = 0; q < 4; ++q) o.v[q] = o.v[q] + cy.v[q];
@@ -337,6 +348,11 @@ struct QuadLanes {
 // handles NC cells along x in each of its rows along y, one row per step.
 // DOT: each wavefront also writes the sum of x_i y_i over its cells (FP64,
 // fixed order) to partial[block]: the p.Ap of a conjugate-gradient iteration.
+template <bool D>
+struct MarchDir {
+  static constexpr bool value = D;
+};
+
 template <class Lanes, bool DOT>
 __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restrict__ x, typename Lanes::T* __restrict__ y,
                                               const ScalarArgs<double>* __restrict__ ap,
@@ -355,10 +371,9 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
   }
   double pq = 0.0;
   const int nvalid = min(NC, nx - ex0);
-  const int nsteps = min((int)(w1 >> 16), ny - ey0);
+  const int nsteps = min((int)((w1 >> 16) & 0x7fffu), ny - ey0);
   const bool hxl = ex0 > 0, hxr = ex0 + nvalid < nx;
-  const size_t row0 = (size_t)nx * ((size_t)ey0 + (size_t)ny * ez);
-  const size_t sy = (size_t)nx * 64, sz = (size_t)nx * ny * 64;  // neighbour strides in values
+  const int64_t sy = (int64_t)nx * 64, sz = (int64_t)nx * ny * 64;  // neighbour strides in values
   const bool hz0 = ez > 0, hz1 = ez < nz - 1;
   // x layout: lane = i1 + 4 i2 + 16 i0, one cell per register
   const int offx = (lane >> 4) + 4 * (lane & 3) + 16 * ((lane >> 2) & 3);
@@ -371,55 +386,69 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
   const double Kz = vz != 0 ? a.Km[2][vz][ai] : op.Kz;
 
-  // own row ey0 to buffer 0, row ey0 - 1 to buffer 1 (invalid or absent
-  // cells as zeros)
-  ln.first_rows(su, su + NC * LCS, x + (row0 + ex0) * 64, sy, nvalid, ey0 > 0);
+  // The march runs up (y increasing) or, where the table entry's top bit is
+  // set, down: odd y-blocks run down, so that the two wavefronts next to a
+  // y-block boundary read the boundary rows at the same time (at both ends
+  // of their marches), from the XCD's L2 rather than twice from HBM.
+  auto march = [&](auto dir) {
+    constexpr bool DOWN = decltype(dir)::value;
+    const int eyf = DOWN ? ey0 + nsteps - 1 : ey0;  // first row of the march
+    const int64_t row0 = (int64_t)nx * ((int64_t)eyf + (int64_t)ny * ez);
+    const int64_t ahead = DOWN ? -sy : sy;  // offset of the next row
+    // first row to buffer 0, the row behind it to buffer 1 (invalid or
+    // absent cells as zeros)
+    ln.first_rows(su, su + NC * LCS, x + (row0 + ex0) * 64, -ahead, nvalid, DOWN ? eyf < ny - 1 : eyf > 0);
 
-  for (int s = 0; s < nsteps; ++s) {
-    const int ey = ey0 + s;
-    const bool hy0 = ey > 0, hy1 = ey < ny - 1;
-    const size_t row = row0 + (size_t)s * nx;
-    const T* __restrict__ xc = x + (row + ex0) * 64;
-    double* cur = su + (s & 1) * (NC * LCS);        // row y
-    double* oth = su + ((s + 1) & 1) * (NC * LCS);  // row y - 1, then row y + 1
+    for (int s = 0; s < nsteps; ++s) {
+      const int ey = DOWN ? eyf - s : eyf + s;
+      const bool hy0 = ey > 0, hy1 = ey < ny - 1;
+      const int64_t row = DOWN ? row0 - (int64_t)s * nx : row0 + (int64_t)s * nx;
+      const T* __restrict__ xc = x + (row + ex0) * 64;
+      double* cur = su + (s & 1) * (NC * LCS);        // row ey
+      double* oth = su + ((s + 1) & 1) * (NC * LCS);  // the row behind, then the row ahead
 
-    const typename Lanes::Rows nr = ln.load_rows(xc, (int64_t)sy, nvalid, hy1);
-    const typename Lanes::Rows zl = ln.load_rows(xc, -(int64_t)sz, nvalid, hz0);
-    const typename Lanes::Rows zr = ln.load_rows(xc, (int64_t)sz, nvalid, hz1);
-    const double xl = hxl ? (double)xc[offx - 64] : 0.0;
-    const double xr = hxr ? (double)xc[64 * nvalid + offx] : 0.0;
+      const typename Lanes::Rows nr = ln.load_rows(xc, ahead, nvalid, DOWN ? hy0 : hy1);
+      const typename Lanes::Rows zl = ln.load_rows(xc, -sz, nvalid, hz0);
+      const typename Lanes::Rows zr = ln.load_rows(xc, sz, nvalid, hz1);
+      const double xl = hxl ? (double)xc[offx - 64] : 0.0;
+      const double xr = hxr ? (double)xc[64 * nvalid + offx] : 0.0;
 
-    // row ey - 1 in the y layout, before the next row replaces it
-    const typename Lanes::Rows yl = ln.lds_y(oth);
-    __syncthreads();
-    ln.store_z(oth, nr);
-    __syncthreads();
-    double ux[NC];
+      // the row behind in the y layout, before the next row replaces it
+      const typename Lanes::Rows yb = ln.lds_y(oth);
+      __syncthreads();
+      ln.store_z(oth, nr);
+      __syncthreads();
+      double ux[NC];
 #pragma unroll
-    for (int k = 0; k < NC; ++k) ux[k] = cur[LCS * k + lx];
+      for (int k = 0; k < NC; ++k) ux[k] = cur[LCS * k + lx];
 
 #pragma unroll
-    for (int k = 0; k < NC; ++k) {
-      if (k < nvalid) {
-        const int ex = ex0 + k;
-        const bool hx0 = ex > 0, hx1 = ex < nx - 1;
-        const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
-        const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
-        double Kx = op.Kx;
-        if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
-        double cx = mfma(Kx, ux[k], 0.0);
-        if (hx0) cx = mfma(op.Lx, ul, cx);
-        if (hx1) cx = mfma(op.Rx, ur, cx);
-        sr[LCS * k + lx] = cx;
+      for (int k = 0; k < NC; ++k) {
+        if (k < nvalid) {
+          const int ex = ex0 + k;
+          const bool hx0 = ex > 0, hx1 = ex < nx - 1;
+          const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
+          const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
+          double Kx = op.Kx;
+          if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
+          double cx = mfma(Kx, ux[k], 0.0);
+          if (hx0) cx = mfma(op.Lx, ul, cx);
+          if (hx1) cx = mfma(op.Rx, ur, cx);
+          sr[LCS * k + lx] = cx;
+        }
       }
+      __syncthreads();
+      const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
+      const double Ky = vy != 0 ? a.Km[1][vy][ai] : op.Ky;
+      ln.template y_stage<DOWN>(cur, oth, sr, yb, Ky, op.Ly, op.Ry, hy0, hy1, nvalid);
+      __syncthreads();
+      ln.template z_stage<DOT>(cur, sr, zl, zr, Kz, op.Lz, op.Rz, hz0, hz1, nvalid, y + (row + ex0) * 64, pq);
     }
-    __syncthreads();
-    const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
-    const double Ky = vy != 0 ? a.Km[1][vy][ai] : op.Ky;
-    ln.y_stage(cur, oth, sr, yl, Ky, op.Ly, op.Ry, hy0, hy1, nvalid);
-    __syncthreads();
-    ln.template z_stage<DOT>(cur, sr, zl, zr, Kz, op.Lz, op.Rz, hz0, hz1, nvalid, y + (row + ex0) * 64, pq);
-  }
+  };
+  if (w1 >> 31)
+    march(MarchDir<true>{});
+  else
+    march(MarchDir<false>{});
   if (DOT) {  // butterfly over the 64 lanes, then lane 0 writes
 #pragma unroll
     for (int m = 32; m > 0; m >>= 1) pq += __shfl_xor(pq, m, 64);
@@ -537,7 +566,8 @@ hipError_t mfma_build(dg_mesh& M, int prec, int rows) {
             for (int cc = c0; cc < c1; ++cc) {
               const int ey0 = yy * rows;
               order[2 * t] = (uint32_t)(cc * NC) | ((uint32_t)ey0 << 16);
-              order[2 * t + 1] = (uint32_t)zz | ((uint32_t)std::min(rows, ny - ey0) << 16);
+              order[2 * t + 1] = (uint32_t)zz | ((uint32_t)std::min(rows, ny - ey0) << 16) |
+                                 ((yy & 1) ? 0x80000000u : 0u);
               ++t;
             }
       }
