@@ -46,9 +46,17 @@
 //    that two neighbouring marches reach the rows of their shared boundary
 //    at the same time. The A-operand entries
 //    of the nine interior-cell operators and the two nodes' tensor weights
-//    form one 96-byte record per lane, read once per wavefront; boundary
-//    cells and rows read their own K variant. Wavefronts are independent
-//    (one per block).
+//    form one 96-byte record per lane, read once per wavefront; the K
+//    variants of the chunk's boundary cells and of the boundary rows are
+//    copied to LDS before the march. Wavefronts are independent (one per
+//    block).
+//  * Global memory is read and written through buffer resources over the
+//    wavefront's window of x and y: absent values (missing neighbours,
+//    cells beyond the mesh) come from out-of-range offsets as zeros, so a
+//    step issues the same reads every time, in the order of use (the next
+//    row, the x-end lines, the z-neighbour rows), and waits only for the
+//    ones needed next: the z-neighbour rows stay in flight through the x
+//    and y stages.
 //  * Results: the x results are written to LDS, the y results added to them
 //    in the y-pair layout, and the z results added on reading them back in
 //    the z-pair layout; the sum times the tensor weight is stored with
@@ -93,29 +101,58 @@ __device__ __forceinline__ double mfma(double a, double b, double c) {
   return __builtin_amdgcn_mfma_f64_4x4x4f64(a, b, c, 0, 0, 0);
 }
 
-// 16-byte load of two doubles (zeros when !v); a native vector type keeps it
-// one dwordx4 load
 typedef double dvec2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ double2 load2(const double* p, bool v) {
-  dvec2 r = {0.0, 0.0};
-  if (v) r = *reinterpret_cast<const dvec2*>(p);
-  return make_double2(r.x, r.y);
-}
+typedef float fvec4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Reads of a wavefront go through a buffer resource over the part of the
+// input vector its march can touch (its window). A lane whose value is absent
+// (a missing neighbour, a cell beyond the mesh) reads at an offset beyond the
+// window and gets zeros from the hardware, without a branch: every step
+// issues the same reads in the same order, so each wait covers only the
+// reads needed next and the later ones stay in flight.
+template <class T>
+struct Window {
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ Window(const T* base, uint32_t bytes)
+      : r(__builtin_amdgcn_make_buffer_rsrc(const_cast<T*>(base), (short)0, (int)bytes, 0x00020000)) {}
+  static __device__ __forceinline__ uint32_t at(int64_t e, bool v) {
+    return v ? (uint32_t)e * (uint32_t)sizeof(T) : 0x80000000u;
+  }
+  // 16 bytes at element e of the window (zeros when !v)
+  __device__ __forceinline__ dvec2 load2(int64_t e, bool v) const {
+    return __builtin_bit_cast(dvec2, __builtin_amdgcn_raw_buffer_load_b128(r, at(e, v), 0, 0));
+  }
+  __device__ __forceinline__ fvec4 load4(int64_t e, bool v) const {
+    return __builtin_bit_cast(fvec4, __builtin_amdgcn_raw_buffer_load_b128(r, at(e, v), 0, 0));
+  }
+  // 16 bytes to element e, non-temporal (dropped when !v)
+  __device__ __forceinline__ void store16(int64_t e, bool v, dvec2 d) const {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, d), r, at(e, v), 0, 2);
+  }
+  __device__ __forceinline__ void store16(int64_t e, bool v, fvec4 d) const {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, d), r, at(e, v), 0, 2);
+  }
+  // one value at element e (zero when !v)
+  __device__ __forceinline__ double load1(int64_t e, bool v) const {
+    if constexpr (sizeof(T) == 8)
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, at(e, v), 0, 0));
+    else
+      return (double)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, at(e, v), 0, 0));
+  }
+};
 
 __device__ __forceinline__ int side_type(bool has, bool dirichlet) {
   return has ? T_INT : (dirichlet ? T_DIR : T_NONE);
 }
 
-typedef float fvec4 __attribute__((ext_vector_type(4)));
-
 struct Quad {
   double v[4];
 };
 
-// 16-byte load of one FP32 x-line (zeros when !ok), widened to FP64
-__device__ __forceinline__ Quad load_quad(const float* p, bool ok) {
-  fvec4 r = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (ok) r = *reinterpret_cast<const fvec4*>(p);
+// one FP32 x-line (zeros when !ok), widened to FP64
+__device__ __forceinline__ Quad load_quad(const Window<float>& w, int64_t e, bool ok) {
+  const fvec4 r = w.load4(e, ok);
   Quad q;
   q.v[0] = (double)r.x;
   q.v[1] = (double)r.y;
@@ -202,22 +239,26 @@ struct PairLanes {
     wn = rec[5];
   }
   // the first row of the march (buffer cur) and the row behind it, at
-  // offset back (buffer oth), of the chunk at xc
-  __device__ __forceinline__ void first_rows(double* cur, double* oth, const double* xc, int64_t back, int nvalid,
-                                             bool has_prev) const {
+  // offset back (buffer oth), of the chunk at element ec of the window
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const Window<double>& w, int64_t ec,
+                                             int64_t back, int nvalid, bool has_prev) const {
 #pragma unroll
     for (int p = 0; p < 2; ++p) {
       const bool v = 2 * p + pc < nvalid;
-      const double2 u0 = load2(xc + 128 * p + offz, v);
-      const double2 um = load2(xc + back + 128 * p + offz, v && has_prev);
-      *reinterpret_cast<double2*>(cur + 2 * LCS * p + lz) = u0;
-      *reinterpret_cast<double2*>(oth + 2 * LCS * p + lz) = um;
+      const dvec2 u0 = w.load2(ec + 128 * p + offz, v);
+      const dvec2 um = w.load2(ec + back + 128 * p + offz, v && has_prev);
+      *reinterpret_cast<dvec2*>(cur + 2 * LCS * p + lz) = u0;
+      *reinterpret_cast<dvec2*>(oth + 2 * LCS * p + lz) = um;
     }
   }
-  __device__ __forceinline__ Rows load_rows(const double* xc, int64_t off, int nvalid, bool ok) const {
+  __device__ __forceinline__ Rows load_rows(const Window<double>& w, int64_t ec, int64_t off, int nvalid,
+                                            bool ok) const {
     Rows r;
 #pragma unroll
-    for (int p = 0; p < 2; ++p) r.v[p] = load2(xc + off + 128 * p + offz, ok && 2 * p + pc < nvalid);
+    for (int p = 0; p < 2; ++p) {
+      const dvec2 u = w.load2(ec + off + 128 * p + offz, ok && 2 * p + pc < nvalid);
+      r.v[p] = make_double2(u.x, u.y);
+    }
     return r;
   }
   __device__ __forceinline__ Rows lds_y(const double* b) const {
@@ -257,7 +298,7 @@ struct PairLanes {
   template <bool DOT>
   __device__ __forceinline__ void z_stage(const double* cur, const double* sr, const Rows& zl, const Rows& zr,
                                           double Kz, double Lz, double Rz, bool hz0, bool hz1, int nvalid,
-                                          double* __restrict__ yc, double& pq) const {
+                                          const Window<double>& yw, int64_t ec, double& pq) const {
     double2 uz[2];
 #pragma unroll
     for (int p = 0; p < 2; ++p) uz[p] = *reinterpret_cast<const double2*>(cur + 2 * LCS * p + lz);
@@ -266,11 +307,10 @@ struct PairLanes {
       if (2 * p < nvalid) {
         const double2 c = pair_line(Kz, Lz, Rz, uz[p], zl.v[p], zr.v[p], hz0, hz1);
         const double2 o = *reinterpret_cast<const double2*>(sr + 2 * LCS * p + lz);
-        if (2 * p + pc < nvalid) {
-          const dvec2 v = {wn.x * (o.x + c.x), wn.y * (o.y + c.y)};
-          __builtin_nontemporal_store(v, reinterpret_cast<dvec2*>(yc + 128 * p + offz));
-          if (DOT) pq = fma(uz[p].y, v.y, fma(uz[p].x, v.x, pq));
-        }
+        const bool ok = 2 * p + pc < nvalid;
+        const dvec2 v = {wn.x * (o.x + c.x), wn.y * (o.y + c.y)};
+        yw.store16(ec + 128 * p + offz, ok, v);
+        if (DOT && ok) pq = fma(uz[p].y, v.y, fma(uz[p].x, v.x, pq));
       }
     }
   }
@@ -299,13 +339,13 @@ struct QuadLanes {
 #pragma unroll
     for (int q = 0; q < 4; ++q) wq[q] = a.lrec[(q >> 1) + 2 * zi1 + 16 * zi2][10 + (q & 1)];
   }
-  __device__ __forceinline__ void first_rows(double* cur, double* oth, const float* xc, int64_t back, int,
-                                             bool has_prev) const {
-    lds_store_quad(cur + lz, load_quad(xc + offz, cok));
-    lds_store_quad(oth + lz, load_quad(xc + back + offz, cok && has_prev));
+  __device__ __forceinline__ void first_rows(double* cur, double* oth, const Window<float>& w, int64_t ec,
+                                             int64_t back, int, bool has_prev) const {
+    lds_store_quad(cur + lz, load_quad(w, ec + offz, cok));
+    lds_store_quad(oth + lz, load_quad(w, ec + back + offz, cok && has_prev));
   }
-  __device__ __forceinline__ Rows load_rows(const float* xc, int64_t off, int, bool ok) const {
-    return load_quad(xc + off + offz, cok && ok);
+  __device__ __forceinline__ Rows load_rows(const Window<float>& w, int64_t ec, int64_t off, int, bool ok) const {
+    return load_quad(w, ec + off + offz, cok && ok);
   }
   __device__ __forceinline__ Rows lds_y(const double* b) const { return lds_quad(b + ly); }
   __device__ __forceinline__ void store_z(double* b, const Rows& r) const { lds_store_quad(b + lz, r); }
@@ -323,7 +363,7 @@ struct QuadLanes {
   template <bool DOT>
   __device__ __forceinline__ void z_stage(const double* cur, const double* sr, const Rows& zl, const Rows& zr,
                                           double Kz, double Lz, double Rz, bool hz0, bool hz1, int,
-                                          float* __restrict__ yc, double& pq) const {
+                                          const Window<float>& yw, int64_t ec, double& pq) const {
     const Quad uz = lds_quad(cur + lz);
     const Quad cz = quad_line(Kz, Lz, Rz, uz, zl, zr, hz0, hz1);
     const Quad o = lds_quad(sr + lz);
@@ -332,14 +372,12 @@ struct QuadLanes {
     v.y = (float)(wq[1] * (o.v[1] + cz.v[1]));
     v.z = (float)(wq[2] * (o.v[2] + cz.v[2]));
     v.w = (float)(wq[3] * (o.v[3] + cz.v[3]));
-    if (cok) {
-      __builtin_nontemporal_store(v, reinterpret_cast<fvec4*>(yc + offz));
-      if (DOT) {
-        pq = fma(uz.v[0], (double)v.x, pq);
-        pq = fma(uz.v[1], (double)v.y, pq);
-        pq = fma(uz.v[2], (double)v.z, pq);
-        pq = fma(uz.v[3], (double)v.w, pq);
-      }
+    yw.store16(ec + offz, cok, v);
+    if (DOT && cok) {
+      pq = fma(uz.v[0], (double)v.x, pq);
+      pq = fma(uz.v[1], (double)v.y, pq);
+      pq = fma(uz.v[2], (double)v.z, pq);
+      pq = fma(uz.v[3], (double)v.w, pq);
     }
   }
 };
@@ -360,6 +398,7 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
   using T = typename Lanes::T;
   __shared__ __attribute__((aligned(16))) double su[2 * NC * LCS];  // own cells of rows y and y + 1
   __shared__ __attribute__((aligned(16))) double sr[NC * LCS];      // x results, then x + y results
+  __shared__ double sk[5][64];                                      // boundary operators
   const ScalarArgs<double>& a = *ap;
   const int lane = threadIdx.x;
   const uint32_t w0 = waves[2 * blockIdx.x], w1 = waves[2 * blockIdx.x + 1];
@@ -386,6 +425,29 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
   const int vz = 3 * side_type(hz0, mask & 16u) + side_type(hz1, mask & 32u);
   const double Kz = vz != 0 ? a.Km[2][vz][ai] : op.Kz;
 
+  // the wavefront's window: every element its march may read (rows ey0 - 1
+  // to ey0 + nsteps of the planes ez - 1 to ez + 1, cells ex0 - 1 to
+  // ex0 + NC), clipped to the vector
+  const int ylo = max(ey0 - 1, 0), yhi = min(ey0 + nsteps, ny - 1);
+  const int zlo = max(ez - 1, 0), zhi = min(ez + 1, nz - 1);
+  const int64_t wlo = ((int64_t)nx * (ylo + (int64_t)ny * zlo) + max(ex0 - 1, 0)) * 64;
+  const int64_t whi = ((int64_t)nx * (yhi + (int64_t)ny * zhi) + min(ex0 + NC + 1, nx)) * 64;
+  const Window<T> win(x + wlo, (uint32_t)((whi - wlo) * (int64_t)sizeof(T)));
+  const Window<T> yw(y + wlo, (uint32_t)((whi - wlo) * (int64_t)sizeof(T)));  // the same range of y
+  // Boundary operators in LDS, read before the march: the x operators of the
+  // chunk's first and last cells (the cells between are interior) and the y
+  // operators of the first row, the last row and a single row. A global
+  // read of them inside a step would sit in a branch, and the wait after it
+  // would also drain the step's z-neighbour reads still in flight.
+  const int exl = ex0 + nvalid - 1;
+  const bool f0 = ex0 > 0, f1 = ex0 < nx - 1, l0 = exl > 0, l1 = exl < nx - 1;
+  const int yb0 = 3 * side_type(false, mask & 4u), yb1 = side_type(false, mask & 8u);
+  sk[0][lane] = a.Km[0][3 * side_type(f0, mask & 1u) + side_type(f1, mask & 2u)][ai];
+  sk[1][lane] = a.Km[0][3 * side_type(l0, mask & 1u) + side_type(l1, mask & 2u)][ai];
+  sk[2][lane] = a.Km[1][yb0][ai];
+  sk[3][lane] = a.Km[1][yb1][ai];
+  sk[4][lane] = a.Km[1][yb0 + yb1][ai];
+
   // The march runs up (y increasing) or, where the table entry's top bit is
   // set, down: odd y-blocks run down, so that the two wavefronts next to a
   // y-block boundary read the boundary rows at the same time (at both ends
@@ -397,21 +459,23 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
     const int64_t ahead = DOWN ? -sy : sy;  // offset of the next row
     // first row to buffer 0, the row behind it to buffer 1 (invalid or
     // absent cells as zeros)
-    ln.first_rows(su, su + NC * LCS, x + (row0 + ex0) * 64, -ahead, nvalid, DOWN ? eyf < ny - 1 : eyf > 0);
+    ln.first_rows(su, su + NC * LCS, win, (row0 + ex0) * 64 - wlo, -ahead, nvalid, DOWN ? eyf < ny - 1 : eyf > 0);
 
     for (int s = 0; s < nsteps; ++s) {
       const int ey = DOWN ? eyf - s : eyf + s;
       const bool hy0 = ey > 0, hy1 = ey < ny - 1;
       const int64_t row = DOWN ? row0 - (int64_t)s * nx : row0 + (int64_t)s * nx;
-      const T* __restrict__ xc = x + (row + ex0) * 64;
+      const int64_t ec = (row + ex0) * 64 - wlo;      // the chunk in the window
       double* cur = su + (s & 1) * (NC * LCS);        // row ey
       double* oth = su + ((s + 1) & 1) * (NC * LCS);  // the row behind, then the row ahead
 
-      const typename Lanes::Rows nr = ln.load_rows(xc, ahead, nvalid, DOWN ? hy0 : hy1);
-      const typename Lanes::Rows zl = ln.load_rows(xc, -sz, nvalid, hz0);
-      const typename Lanes::Rows zr = ln.load_rows(xc, sz, nvalid, hz1);
-      const double xl = hxl ? (double)xc[offx - 64] : 0.0;
-      const double xr = hxr ? (double)xc[64 * nvalid + offx] : 0.0;
+      // in the order of use: the next row (stored to LDS first), the x-end
+      // lines (the x stage), the z-neighbour rows (the z stage, last)
+      const typename Lanes::Rows nr = ln.load_rows(win, ec, ahead, nvalid, DOWN ? hy0 : hy1);
+      const double xl = win.load1(ec + offx - 64, hxl);
+      const double xr = win.load1(ec + 64 * nvalid + offx, hxr);
+      const typename Lanes::Rows zl = ln.load_rows(win, ec, -sz, nvalid, hz0);
+      const typename Lanes::Rows zr = ln.load_rows(win, ec, sz, nvalid, hz1);
 
       // the row behind in the y layout, before the next row replaces it
       const typename Lanes::Rows yb = ln.lds_y(oth);
@@ -430,7 +494,7 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
           const double ul = k == 0 ? xl : ux[k > 0 ? k - 1 : 0];
           const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
           double Kx = op.Kx;
-          if (!(hx0 && hx1)) Kx = a.Km[0][3 * side_type(hx0, mask & 1u) + side_type(hx1, mask & 2u)][ai];
+          if (!(hx0 && hx1)) Kx = sk[k == 0 ? 0 : 1][lane];
           double cx = mfma(Kx, ux[k], 0.0);
           if (hx0) cx = mfma(op.Lx, ul, cx);
           if (hx1) cx = mfma(op.Rx, ur, cx);
@@ -438,11 +502,10 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
         }
       }
       __syncthreads();
-      const int vy = 3 * side_type(hy0, mask & 4u) + side_type(hy1, mask & 8u);
-      const double Ky = vy != 0 ? a.Km[1][vy][ai] : op.Ky;
+      const double Ky = hy0 && hy1 ? op.Ky : sk[hy1 ? 2 : (hy0 ? 3 : 4)][lane];
       ln.template y_stage<DOWN>(cur, oth, sr, yb, Ky, op.Ly, op.Ry, hy0, hy1, nvalid);
       __syncthreads();
-      ln.template z_stage<DOT>(cur, sr, zl, zr, Kz, op.Lz, op.Rz, hz0, hz1, nvalid, y + (row + ex0) * 64, pq);
+      ln.template z_stage<DOT>(cur, sr, zl, zr, Kz, op.Lz, op.Rz, hz0, hz1, nvalid, yw, ec, pq);
     }
   };
   if (w1 >> 31)
@@ -509,8 +572,18 @@ int mfma_default_rows(int nx, int ny, int nz) {
   return 1;
 }
 
+// A wavefront's window (two planes and the march's rows around it) must stay
+// below 2 GiB: its reads take 32-bit byte offsets, and the offsets above it
+// mark the absent values.
+static bool mfma_window_fits(int nx, int ny, int rows) {
+  const int64_t cells = 2LL * nx * ny + (int64_t)(rows + 2) * nx + NC + 2;
+  return cells * 64 * (int64_t)sizeof(double) < (1LL << 31);
+}
+
 hipError_t mfma_setup(dg_mesh& M) {
   if (M.p != 4) return hipSuccess;
+  // meshes with larger planes run the line kernels
+  if (!mfma_window_fits(M.desc.nx, M.desc.ny, NYMAX)) return hipSuccess;
   hipError_t e = mfma_build(M, DG_F64, 0);
   if (e != hipSuccess) return e;
   return mfma_build(M, DG_F32, 0);
@@ -524,7 +597,7 @@ hipError_t mfma_build(dg_mesh& M, int prec, int rows) {
   if (rows > NYMAX) return hipErrorInvalidValue;
   const int nyb = (ny + rows - 1) / rows;
   const int64_t W = (int64_t)nc * nyb * nz;
-  if (W > 0x7fffffff / 2) return hipErrorInvalidValue;
+  if (W > 0x7fffffff / 2 || !mfma_window_fits(nx, ny, rows)) return hipErrorInvalidValue;
   // One region of the mesh per XCD: the split (rx, ry, rz), rx ry rz = 8, that
   // reads the fewest cells across region boundaries (each XCD has its own
   // L2, so a neighbour cell of another region is fetched again).
