@@ -280,7 +280,10 @@ dg_status dg_residual(const dg_mesh* mesh, int precision, const void* u, void* r
  *     line kernels (thread per 1D line).
  * Without a call the cost model's choice is in use: the matrix-core kernel
  * where it exists, with the most rows (up to 16) that leave at least 4096
- * wavefronts, and the region sweep. All variants compute the same operator;
+ * wavefronts, and the region sweep. The matrix-core kernel exists for k = 3,
+ * kappa = 1, diffusion-reaction, on meshes whose x-y planes hold at most about
+ * two million cells (a wavefront addresses two planes of FP64 values with
+ * 32-bit byte offsets); larger planes run the line kernels. All variants compute the same operator;
  * the matrix-core variants and the two sweep orders give bitwise the same
  * results among themselves. The sweep order is shared by both precisions and
  * by the other line kernels of the mesh (preconditioner, adjoint, load

@@ -169,6 +169,33 @@ def test_q3_row_march_ragged(gpu_lib, shape, mask):
     assert relerr(y, ref) < TOL64
 
 
+def test_q3_wide_planes_run_the_line_kernels(gpu_lib):
+    """A Q3 mesh of 1500 x 1500 x 1 cells (144M DOFs): a wavefront of the
+    matrix-core kernel reads within two x-y planes through 32-bit byte
+    offsets, and planes this wide exceed that window, so the mesh offers no
+    matrix-core variant and its apply runs the line kernels; their result
+    matches the oracle's block rows on sampled cells (corners, edges,
+    natural and Dirichlet sides, random cells), relative L2 and elementwise."""
+    dg = gpu_lib
+    nx, ny, nz, mask = 1500, 1500, 1, 0x2D
+    E = nx * ny * nz
+    print(f"case: Q3 wide planes {nx}x{ny}x{nz} mask={mask:#x}", flush=True)
+    mesh = dg.Mesh(dg.make_desc(nx, ny, nz, k=3, dirichlet_mask=mask))
+    with pytest.raises(dg.DGError) as ei:
+        dg.dg_mesh_set_variant(mesh.handle, 0, dg.DG_VARIANT_MATRIX_CORE, 16)
+    assert ei.value.status == dg.DG_ERR_ARG
+    x = workloads.uniform(E * 64, 6200)
+    y = mesh.apply(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(6201)
+    fixed = [0, nx - 1, nx * (ny - 1), E - 1, nx * (ny // 2), nx * (ny // 2) + nx - 1, E // 2 + 7]
+    cells = np.unique(np.concatenate([fixed, rng.choice(E, 57, replace=False)]))
+    got = y.cpu().numpy().reshape(E, 64)[cells]
+    ref = ScalarDG(Problem(nx, ny, nz, k=3, mask=mask)).apply_rows(x, cells)
+    assert relerr(got, ref) < TOL64
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
 def test_q5_40cube_full_vector(gpu_lib):
     """The Q5 40^3 solve workload (13.8M DOFs) at full size, FP64 (line-operator
     kernel) and FP32 (sum-factorized kernel), against the oracle's deduplicated BSR."""
