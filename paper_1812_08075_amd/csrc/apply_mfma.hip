@@ -53,10 +53,10 @@
 //  * Global memory is read and written through buffer resources over the
 //    wavefront's window of x and y: absent values (missing neighbours,
 //    cells beyond the mesh) come from out-of-range offsets as zeros, so a
-//    step issues the same reads every time, in the order of use (the next
-//    row, the x-end lines, the z-neighbour rows), and waits only for the
-//    ones needed next: the z-neighbour rows stay in flight through the x
-//    and y stages.
+//    step issues the same reads every time, in the order of use (the x-end
+//    lines, the next row, the z-neighbour rows), and waits only for the
+//    ones needed next: the next row arrives during the x stage, the
+//    z-neighbour rows during the x and y stages.
 //  * Results: the x results are written to LDS, the y results added to them
 //    in the y-pair layout, and the z results added on reading them back in
 //    the z-pair layout; the sum times the tensor weight is stored with
@@ -469,18 +469,20 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
       double* cur = su + (s & 1) * (NC * LCS);        // row ey
       double* oth = su + ((s + 1) & 1) * (NC * LCS);  // the row behind, then the row ahead
 
-      // in the order of use: the next row (stored to LDS first), the x-end
-      // lines (the x stage), the z-neighbour rows (the z stage, last)
-      const typename Lanes::Rows nr = ln.load_rows(win, ec, ahead, nvalid, DOWN ? hy0 : hy1);
+      // in the order of use: the x-end lines (the x stage), the next row
+      // (stored to LDS after the x stage), the z-neighbour rows (the z stage)
+      // (empty asm statements with a memory clobber pin that order: the
+      // wait for a read also waits for every read issued before it)
       const double xl = win.load1(ec + offx - 64, hxl);
       const double xr = win.load1(ec + 64 * nvalid + offx, hxr);
+      asm volatile("" ::: "memory");
+      const typename Lanes::Rows nr = ln.load_rows(win, ec, ahead, nvalid, DOWN ? hy0 : hy1);
+      asm volatile("" ::: "memory");
       const typename Lanes::Rows zl = ln.load_rows(win, ec, -sz, nvalid, hz0);
       const typename Lanes::Rows zr = ln.load_rows(win, ec, sz, nvalid, hz1);
 
       // the row behind in the y layout, before the next row replaces it
       const typename Lanes::Rows yb = ln.lds_y(oth);
-      __syncthreads();
-      ln.store_z(oth, nr);
       __syncthreads();
       double ux[NC];
 #pragma unroll
@@ -495,12 +497,18 @@ __device__ __forceinline__ void apply_q3_wave(const typename Lanes::T* __restric
           const double ur = k == nvalid - 1 ? xr : ux[k + 1 < NC ? k + 1 : k];
           double Kx = op.Kx;
           if (!(hx0 && hx1)) Kx = sk[k == 0 ? 0 : 1][lane];
+          // without a neighbour the x-end line read zeros, and its term adds
+          // zero: no branch, so the compiler keeps the x-end reads where they
+          // are issued instead of sinking them into the branch
           double cx = mfma(Kx, ux[k], 0.0);
-          if (hx0) cx = mfma(op.Lx, ul, cx);
-          if (hx1) cx = mfma(op.Rx, ur, cx);
+          cx = mfma(op.Lx, ul, cx);
+          cx = mfma(op.Rx, ur, cx);
           sr[LCS * k + lx] = cx;
         }
       }
+      // the next row replaces the row behind only now, so that its read
+      // has the x stage to arrive
+      ln.store_z(oth, nr);
       __syncthreads();
       const double Ky = hy0 && hy1 ? op.Ky : sk[hy1 ? 2 : (hy0 ? 3 : 4)][lane];
       ln.template y_stage<DOWN>(cur, oth, sr, yb, Ky, op.Ly, op.Ry, hy0, hy1, nvalid);
