@@ -114,6 +114,43 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 constexpr int FG = 33;
 constexpr int FG_AL1 = 0, FG_AL2 = 3, FG_BE = 6, FG_OWN = 9, FG_NB = 21;
 
+// Values of other lanes of the wavefront by DPP, without LDS. quad_bcast<J>:
+// every lane gets the value of lane J of its group of four; row_rot<R>: lane
+// i gets the value of lane i - R (mod 16) of its 16-lane row (row_ror).
+template <int J>
+__device__ __forceinline__ double quad_bcast(double v) {
+  constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int R>
+__device__ __forceinline__ double row_rot(double v) {
+  if constexpr (R == 0) return v;
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x120 + R, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x120 + R, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// k = 3: a face's 16 points fill one 16-lane row, point (pa, pb) in lane
+// pa + 4 pb of it. Derivatives of a face field along the two tangential
+// directions (Σ_j D[pa][j] v(j, pb) and Σ_j D[pb][j] v(pa, j)) from the
+// lanes' own values; pbs[k] = pb - k (mod 4) is the pb of the point whose
+// value row_rot<4k> brings.
+__device__ __forceinline__ void face_tangential4(const double* __restrict__ tD, int pa, int pb, const int* pbs,
+                                                 double v, double& ga, double& gb) {
+  ga = fma(tD[pa * 4 + 0], quad_bcast<0>(v), 0.0);
+  ga = fma(tD[pa * 4 + 1], quad_bcast<1>(v), ga);
+  ga = fma(tD[pa * 4 + 2], quad_bcast<2>(v), ga);
+  ga = fma(tD[pa * 4 + 3], quad_bcast<3>(v), ga);
+  gb = fma(tD[pb * 4 + pbs[0]], v, 0.0);
+  gb = fma(tD[pb * 4 + pbs[1]], row_rot<4>(v), gb);
+  gb = fma(tD[pb * 4 + pbs[2]], row_rot<8>(v), gb);
+  gb = fma(tD[pb * 4 + pbs[3]], row_rot<12>(v), gb);
+}
+
 template <int P>
 __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double* __restrict__ y, const StokesArgs& a,
                                             const StokesGeom& geo) {
@@ -397,6 +434,14 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
     const int lb = (t / L) * L;  // first point of the thread's face in the round
     double* sT = X;               // own velocity traces [3][RP]
     double* sN = X + 3 * RP;      // neighbour's
+    // k = 3: the tangential derivatives of the traces come from the face's
+    // other lanes (DPP) instead of LDS reads along the face's lines
+    constexpr bool LANES = P == 4;
+    // row_ror:n gives lane i the value of lane i - n (mod 16) of its row, so
+    // row_rot<4k> brings the value of point (pa, pb - k mod 4)
+    int pbs[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) pbs[k] = (pb - k) & 3;
     double dnT[3] = {0.0, 0.0, 0.0}, dnN[3] = {0.0, 0.0, 0.0};
     const bool has_nb = valid && has_nb_of(f);
     if (valid) {
@@ -490,13 +535,18 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           double ga = 0, gb = 0;
+          if constexpr (LANES) {
+            uT[c] = sT[c * RP + t];
+            face_tangential4(tD, pa, pb, pbs, uT[c], ga, gb);
+          } else {
 #pragma unroll
-          for (int j = 0; j < P; ++j) {
-            ga = fma(tD[pa * P + j], sT[c * RP + lb + j + P * pb], ga);
-            gb = fma(tD[pb * P + j], sT[c * RP + lb + pa + P * j], gb);
+            for (int j = 0; j < P; ++j) {
+              ga = fma(tD[pa * P + j], sT[c * RP + lb + j + P * pb], ga);
+              gb = fma(tD[pb * P + j], sT[c * RP + lb + pa + P * j], gb);
+            }
+            uT[c] = sT[c * RP + t];
           }
           gT[c] = fma(Jd, dnT[c], fma(J1, ga, J2 * gb));
-          uT[c] = sT[c * RP + t];
         }
         const double pA = fpA[fp];
         int t1, t2;
@@ -512,14 +562,20 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
           const double Nd = kb * nn2, N1 = kb * fma(g12, p2, -g22 * p1), N2 = kb * fma(g12, p1, -g11 * p2);
 #pragma unroll
           for (int c = 0; c < 3; ++c) {
-            double ga = 0, gb = 0;
+            double ga = 0, gb = 0, uN;
+            if constexpr (LANES) {
+              uN = sN[c * RP + t];
+              face_tangential4(tD, pa, pb, pbs, uN, ga, gb);
+            } else {
 #pragma unroll
-            for (int j = 0; j < P; ++j) {
-              ga = fma(tD[pa * P + j], sN[c * RP + lb + j + P * pb], ga);
-              gb = fma(tD[pb * P + j], sN[c * RP + lb + pa + P * j], gb);
+              for (int j = 0; j < P; ++j) {
+                ga = fma(tD[pa * P + j], sN[c * RP + lb + j + P * pb], ga);
+                gb = fma(tD[pb * P + j], sN[c * RP + lb + pa + P * j], gb);
+              }
+              uN = sN[c * RP + t];
             }
             const double gN = fma(Nd, dnN[c], fma(N1, ga, N2 * gb));
-            const double jump = uT[c] - sN[c * RP + t];
+            const double jump = uT[c] - uN;
             Rv[c] = dA * (fma(-0.5, gT[c] + gN, gam * jump) + pA * nu[c]);
             Rg[c] = dA * 0.5 * a.theta * jump;
             Rq = fma(dA * 0.5 * jump, nu[c], Rq);
@@ -544,7 +600,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
     __syncthreads();
     double* sJ1 = X;            // Rg (grad xi_t1 . nu) [3][RP]
     double* sJ2 = X + 3 * RP;   // Rg (grad xi_t2 . nu)
-    if (valid) {
+    if (!LANES && valid) {
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         sJ1[c * RP + t] = RJ1[c];
@@ -558,10 +614,21 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         double v = Rv[c];
+        if constexpr (LANES) {
+          v = fma(tD[0 * 4 + pa], quad_bcast<0>(RJ1[c]), v);
+          v = fma(tD[pbs[0] * 4 + pb], RJ2[c], v);
+          v = fma(tD[1 * 4 + pa], quad_bcast<1>(RJ1[c]), v);
+          v = fma(tD[pbs[1] * 4 + pb], row_rot<4>(RJ2[c]), v);
+          v = fma(tD[2 * 4 + pa], quad_bcast<2>(RJ1[c]), v);
+          v = fma(tD[pbs[2] * 4 + pb], row_rot<8>(RJ2[c]), v);
+          v = fma(tD[3 * 4 + pa], quad_bcast<3>(RJ1[c]), v);
+          v = fma(tD[pbs[3] * 4 + pb], row_rot<12>(RJ2[c]), v);
+        } else {
 #pragma unroll
-        for (int q = 0; q < P; ++q) {
-          v = fma(tD[q * P + pa], sJ1[c * RP + lb + q + P * pb], v);
-          v = fma(tD[q * P + pb], sJ2[c * RP + lb + pa + P * q], v);
+          for (int q = 0; q < P; ++q) {
+            v = fma(tD[q * P + pa], sJ1[c * RP + lb + q + P * pb], v);
+            v = fma(tD[q * P + pb], sJ2[c * RP + lb + pa + P * q], v);
+          }
         }
         Rv[c] = v;
       }
@@ -652,9 +719,10 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
   }
 }
 
-// k = 3: at most 128 VGPRs, so that four wavefronts fit per SIMD beside the
-// 10 KB of LDS per cell
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+// k = 3: at most 168 VGPRs (three wavefronts per SIMD; the 10 KB of LDS per
+// cell allow fifteen per CU), enough to keep the DPP face contractions free
+// of spills
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(3)))
     k_stokes_apply_q3(const double* __restrict__ x, double* __restrict__ y, const StokesArgs a, const StokesGeom geo) {
   stokes_cell<4>(x, y, a, geo);
 }
