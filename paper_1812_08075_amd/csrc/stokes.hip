@@ -52,6 +52,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "lane_dpp.h"
 
 namespace dgi {
 namespace {
@@ -113,43 +114,6 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
 // at 3 m + k).
 constexpr int FG = 33;
 constexpr int FG_AL1 = 0, FG_AL2 = 3, FG_BE = 6, FG_OWN = 9, FG_NB = 21;
-
-// Values of other lanes of the wavefront by DPP, without LDS. quad_bcast<J>:
-// every lane gets the value of lane J of its group of four; row_rot<R>: lane
-// i gets the value of lane i - R (mod 16) of its 16-lane row (row_ror).
-template <int J>
-__device__ __forceinline__ double quad_bcast(double v) {
-  constexpr int ctrl = J | (J << 2) | (J << 4) | (J << 6);
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, ctrl, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), ctrl, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-template <int R>
-__device__ __forceinline__ double row_rot(double v) {
-  if constexpr (R == 0) return v;
-  const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, 0x120 + R, 0xf, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), 0x120 + R, 0xf, 0xf, false);
-  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-// k = 3: a face's 16 points fill one 16-lane row, point (pa, pb) in lane
-// pa + 4 pb of it. Derivatives of a face field along the two tangential
-// directions (Σ_j D[pa][j] v(j, pb) and Σ_j D[pb][j] v(pa, j)) from the
-// lanes' own values; pbs[k] = pb - k (mod 4) is the pb of the point whose
-// value row_rot<4k> brings.
-__device__ __forceinline__ void face_tangential4(const double* __restrict__ tD, int pa, int pb, const int* pbs,
-                                                 double v, double& ga, double& gb) {
-  ga = fma(tD[pa * 4 + 0], quad_bcast<0>(v), 0.0);
-  ga = fma(tD[pa * 4 + 1], quad_bcast<1>(v), ga);
-  ga = fma(tD[pa * 4 + 2], quad_bcast<2>(v), ga);
-  ga = fma(tD[pa * 4 + 3], quad_bcast<3>(v), ga);
-  gb = fma(tD[pb * 4 + pbs[0]], v, 0.0);
-  gb = fma(tD[pb * 4 + pbs[1]], row_rot<4>(v), gb);
-  gb = fma(tD[pb * 4 + pbs[2]], row_rot<8>(v), gb);
-  gb = fma(tD[pb * 4 + pbs[3]], row_rot<12>(v), gb);
-}
 
 template <int P>
 __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double* __restrict__ y, const StokesArgs& a,
@@ -537,7 +501,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
           double ga = 0, gb = 0;
           if constexpr (LANES) {
             uT[c] = sT[c * RP + t];
-            face_tangential4(tD, pa, pb, pbs, uT[c], ga, gb);
+            grid4_rows(tD, pa, pb, uT[c], ga, gb);
           } else {
 #pragma unroll
             for (int j = 0; j < P; ++j) {
@@ -565,7 +529,7 @@ __device__ __forceinline__ void stokes_cell(const double* __restrict__ x, double
             double ga = 0, gb = 0, uN;
             if constexpr (LANES) {
               uN = sN[c * RP + t];
-              face_tangential4(tD, pa, pb, pbs, uN, ga, gb);
+              grid4_rows(tD, pa, pb, uN, ga, gb);
             } else {
 #pragma unroll
               for (int j = 0; j < P; ++j) {
