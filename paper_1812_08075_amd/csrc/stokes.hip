@@ -37,11 +37,14 @@
 //     own trace of u and its normal derivative are the line's dot products
 //     with l_j(s), l'_j(s) (normal direction first, Section 2.2); the
 //     neighbour's come from its line in global memory; tangential
-//     derivatives are D-contractions across the face points (through LDS).
-//     The flux gives, per point, the coefficient of the test function's value
-//     and of its gradient along nu; the tangential parts of the latter are
-//     contracted across the face points (D^T) once per point, and every node
-//     then adds l_j(s) and l'_j(s) times its face's two coefficients.
+//     derivatives are D-contractions across the face points. The flux gives,
+//     per point, the coefficient of the test function's value and of its
+//     gradient along nu; the tangential parts of the latter are contracted
+//     across the face points (D^T) once per point, and every node then adds
+//     l_j(s) and l'_j(s) times its face's two coefficients. At k = 3 a face's
+//     16 points fill one 16-lane row, so both contractions across the face
+//     points take their operands from the neighbouring lanes by DPP; at k = 2
+//     (9 points per face) they go through LDS.
 //  4. pressure test functions: the cell residual and the faces' [u].n terms
 //     through A_p^T (x) A_p^T (x) A_p^T and e_p (x) A_p^T (x) A_p^T.
 // Every output entry has one writer; no atomics; bitwise reproducible.
